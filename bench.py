@@ -1,0 +1,205 @@
+"""Benchmark of the bake-off hot path on one MI355X.
+
+Default workload: BP5 (stiffness, GLL q = N+1, Dirichlet), N = 7, perturbed
+brick of E = 64^3 elements (n = N^3 E = 89,915,392 points), uniform[-1,1]
+right-hand side (seed 0), Jacobi-PCG with a fixed iteration count (the
+paper's timing mode). One step = one CG iteration: operator apply with
+gather/scatter, the two fused vector updates and their reductions.
+
+python bench.py [--gpus 1] [--steps 100] [--warmup 20] [--sweep] [--no-cpu]
+
+Prints one JSON line (rank 0). DOFs/s = iterations * n / seconds with
+n = N^3 E (section 2); the unique-node count is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "BP5 DOFs/s (CG iters×n/s) at N=7 + n_0.8 on 1 MI355X; % HBM roofline"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0):
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2004_06722_amd.bp as B
+    q, quad = B.bp_quadrature(bp, N)
+    ex, ey, ez = synth.element_grid(k)
+    xi, _ = B.rule(N + 1, B.GLL)
+    mesh = synth.brick_mesh(ex, ey, ez, N, xi, seed=0)
+    dirich = mesh.boundary if bp >= 3 else None
+    op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp)
+    b = synth.rhs_uniform(mesh.nglobal, seed, ncomp=ncomp, dirichlet=dirich)
+    bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    info = {"E": ex * ey * ez, "grid": [ex, ey, ez], "n": N ** 3 * ex * ey * ez,
+            "n_unique": int(mesh.nglobal)}
+    del mesh
+    return op, bd, info
+
+
+def time_solve(op, b, steps: int, warmup: int):
+    import torch
+    import paper_2004_06722_amd.bp as B
+    if warmup:
+        op.pcg_solve(b, maxit=warmup, fixed_iters=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = op.pcg_solve(b, maxit=steps, fixed_iters=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, st
+
+
+def cpu_baseline(N: int, target_s: float = 15.0):
+    """The oracle's Jacobi-PCG on BP5 at E = 16^3, timed on the host."""
+    import numpy as np
+
+    import synth
+    from oracle.operators import STIFF, Discretization
+    from oracle.pcg import pcg
+    from oracle.quadrature import bp_rule
+    k = 12
+    ex, ey, ez = synth.element_grid(k)
+    rule = bp_rule(5, N)
+    mesh = synth.brick_mesh(ex, ey, ez, N, rule.xi, seed=0)
+    disc = Discretization(rule, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, mesh.boundary)
+    b = synth.rhs_uniform(mesh.nglobal, 0, dirichlet=mesh.boundary)
+    dinv = disc.jacobi_inverse(STIFF)
+    A = lambda v: disc.apply(STIFF, v)
+    t0 = time.perf_counter()
+    pcg(A, b, dinv, maxit=1, fixed_iters=True)
+    one = time.perf_counter() - t0
+    iters = max(2, min(100, int(target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    pcg(A, b, dinv, maxit=iters, fixed_iters=True)
+    dt = time.perf_counter() - t0
+    n = N ** 3 * ex * ey * ez
+    threads = 1   # numpy einsum / add.at paths of the oracle run on one thread
+    return {"value": iters * n / dt, "unit": "DOFs/s", "cores": threads, "kind": "oracle",
+            "sample": f"BP5 N={N} E={ex}x{ey}x{ez} (n={n}), {iters} PCG iterations, "
+                      f"{dt:.1f} s, numpy {np.__version__}, host {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs visible"}
+
+
+def n08_from_sweep(points):
+    """r_max, n_0.8 (log-interpolated first crossing of 0.8 r_max), t_0.8."""
+    pts = sorted(points)
+    rmax = max(r for _, r in pts)
+    target = 0.8 * rmax
+    n08 = None
+    for (n0, r0), (n1, r1) in zip(pts, pts[1:]):
+        if r0 < target <= r1:
+            f = (target - r0) / (r1 - r0)
+            n08 = math.exp(math.log(n0) + f * (math.log(n1) - math.log(n0)))
+            break
+    if n08 is None and pts[0][1] >= target:
+        n08 = pts[0][0]
+    return rmax, n08, (1.25 * n08 / rmax if n08 else None)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--N", type=int, default=7)
+    ap.add_argument("--k", type=int, default=18, help="E = 2^k elements (default 64^3)")
+    ap.add_argument("--sweep", action="store_true", help="E = 2^k sweep for n_0.8")
+    ap.add_argument("--sweep-k", default="5:18")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU decomposition is described but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2004_06722_amd.bp as B
+    from paper_2004_06722_amd import model
+    from paper_2004_06722_amd._lib import BP_OPT_TIME_APPLY
+    torch.cuda.set_device(0)
+    bp, N, k = 5, args.N, args.k
+
+    log(f"setup BP{bp} N={N} E=2^{k}")
+    t0 = time.perf_counter()
+    op, b, info = build_problem(bp, N, k)
+    log(f"setup done in {time.perf_counter() - t0:.1f} s: n={info['n']} unique={info['n_unique']}")
+    op.set_option(BP_OPT_TIME_APPLY, 1)
+    wall, st = time_solve(op, b, args.steps, args.warmup)
+    log(f"timed {args.steps} iterations: wall {wall * 1e3:.2f} ms, loop {st['ms']:.2f} ms")
+    n, E = info["n"], info["E"]
+    value = args.steps * n / wall
+    apply_avg_ms = st["apply_ms"] / max(st["apply_count"], 1)
+    ab = model.apply_bytes(bp, N, E)
+    achieved = ab / (apply_avg_ms * 1e-3) / 1e9
+    it_bytes = model.iteration_bytes(bp, N, E)
+    loop_s = st["ms"] * 1e-3
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded perturbed brick mesh, uniform[-1,1] rhs)",
+        "config": {"workload": f"BP5 scalar Poisson, GLL q=N+1, N={N}, E={info['grid'][0]}x"
+                               f"{info['grid'][1]}x{info['grid'][2]}, Jacobi-PCG fixed "
+                               f"{args.steps} iterations",
+                   "N": N, "E": E, "n": n, "n_unique": info["n_unique"]},
+        "roofline": {"bound": "hbm", "kernel": f"k_stiff_colloc<{N + 1},1,double>",
+                     "achieved": achieved, "peak": model.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / model.HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": ab, "avg_launch_ms": apply_avg_ms},
+        "iteration": {"algorithmic_GBs": it_bytes * args.steps / loop_s / 1e9,
+                      "frac_hbm": it_bytes * args.steps / loop_s / 1e9 / model.HBM_PEAK_GBS,
+                      "fp64_TFLOPs": model.iteration_flops(bp, N, E) * args.steps / loop_s / 1e12,
+                      "DOFs_per_s_unique": args.steps * info["n_unique"] / wall,
+                      "loop_ms": st["ms"]},
+    }
+    op.close()
+    del b
+    torch.cuda.empty_cache()
+
+    if args.sweep:
+        lo, hi = (int(x) for x in args.sweep_k.split(":"))
+        pts = []
+        for kk in range(lo, hi + 1):
+            o2, b2, inf2 = build_problem(bp, N, kk)
+            w2, st2 = time_solve(o2, b2, 100, 10)
+            r = 100 * inf2["n"] / w2
+            pts.append((inf2["n"], r))
+            log(f"sweep E=2^{kk}: n={inf2['n']} {r:.3e} DOFs/s")
+            o2.close()
+            del b2
+        rmax, n08, t08 = n08_from_sweep(pts)
+        result["sweep"] = {"points": [[a, b_] for a, b_ in pts], "r_max": rmax, "n_0.8": n08,
+                           "t_0.8_s": t08}
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        result["cpu_baseline"] = cpu_baseline(N)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

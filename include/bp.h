@@ -1,0 +1,203 @@
+/*
+ * bp.h -- C ABI of the MI355X bake-off library (BP1-BP6 hot path).
+ *
+ * The library applies the assembled high-order hexahedral mass matrix B and
+ * stiffness matrix A of the bake-off problems matrix-free (sum factorisation,
+ * section 5, eq. (bk5x) and (mass)), with the element gather u_L = Q u and the
+ * scatter-add w = Q^T w_L of section 4, and runs the diagonally (Jacobi)
+ * preconditioned CG iteration of section 3 around them, on one HIP device.
+ *
+ * Conventions shared by every entry point
+ *   - p is the polynomial order, p1 = p + 1 nodes per direction (GLL points),
+ *     q quadrature points per direction (section 3, Table "bps": GL q = p+2
+ *     for BP1-BP4, GLL q = p+1 for BP5-BP6).
+ *   - Element-local node (i, j, k) has local id l = i + p1*(j + p1*k), i the
+ *     fastest index (eq. (xijk)/(uijk)); quadrature point (a, b, c) likewise.
+ *   - Global vectors are device arrays [nglobal][ncomp] (components
+ *     interleaved, component fastest), FP64 unless stated.
+ *   - Every call that takes a `stream` enqueues its device work on that HIP
+ *     stream (hipStream_t passed as void*, NULL = the null stream) and returns
+ *     without waiting, unless stated otherwise.
+ *   - Return value: BP_OK (0) or a negative bp_status. bp_last_error()
+ *     returns a message for the calling thread's last failure.
+ *   - Device pointers are owned by the caller; the library never frees them.
+ *     Everything the library allocates belongs to the bp_op and is freed by
+ *     bp_destroy.
+ */
+#ifndef BP_H
+#define BP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bp_op_s *bp_op; /* opaque, owned by the library */
+
+enum bp_status {
+  BP_OK = 0,
+  BP_ERR_ARG = -1,        /* invalid argument or unsupported combination   */
+  BP_ERR_MESH = -2,       /* bad mesh: Jacobian <= 0, index out of range    */
+  BP_ERR_HIP = -3,        /* a HIP runtime call failed                       */
+  BP_ERR_NONFINITE = -4,  /* NaN or Inf in an input or a reduction           */
+  BP_ERR_BREAKDOWN = -5,  /* CG breakdown: p.Ap <= 0 with p != 0             */
+  BP_ERR_OOM = -6         /* device or host allocation failed                */
+};
+
+enum bp_quad { BP_QUAD_GL = 0, BP_QUAD_GLL = 1 };
+enum bp_which { BP_MASS = 1, BP_STIFF = 3 };
+enum bp_prec { BP_FP64 = 0, BP_FP32 = 1 };
+
+/* flags of bp_apply / bp_diag */
+#define BP_MASKED 1u          /* w = mask * A (mask * u), mask = 0 on Dirichlet nodes */
+/* flags of bp_setup */
+#define BP_SETUP_FP32 1u      /* also keep single-precision geometric factors and
+                                 workspace for prec = BP_FP32 and the mixed solve   */
+
+/* Version of this ABI (major*100 + minor). */
+int bp_version(void);
+
+/*
+ * bp_rule -- host-only: the library's 1D rule with n points.
+ * Section 3 / Table "bps": GLL (quad = BP_QUAD_GLL, n >= 2) or GL
+ * (BP_QUAD_GL, n >= 1) points on [-1, 1], ascending, and their weights.
+ * x, w: host arrays of n doubles (w may be NULL). No device work.
+ * Callers use it to place mesh nodes at the library's own GLL points.
+ */
+int bp_rule(int n, int quad, double *x, double *w);
+
+/*
+ * bp_setup -- build an operator on the current HIP device.
+ * Section 4 (isoparametric elements, eq. (xijk); global-to-local map Q,
+ * eq. (dssum)) and section 5 (geometric factors G, eq. (gij); B~, eq. (mass)),
+ * all precomputed as section 3 requires.
+ *   p in [1, 15]; q in [2, 16]; quad = BP_QUAD_GL or BP_QUAD_GLL (GLL needs
+ *   q = p + 1, collocated); ncomp in [1, 8] components per node.
+ *   The compiled kernels cover p <= 8 with (quad, q) = (GLL, p+1) or
+ *   (GL, p+2); other combinations return BP_ERR_ARG.
+ *   nelem >= 1; nglobal in [1, 2^31 - 1].
+ *   elem_dofs: host int64 [nelem][p1^3], global node id of each local node,
+ *     0 <= id < nglobal. The map is treated as arbitrary (no tensor layout).
+ *   node_xyz: host double [nelem][p1^3][3], coordinates of the element nodes
+ *     (placed at the GLL points of the reference element).
+ *   dirichlet: host uint8 [nglobal] (nonzero = homogeneous Dirichlet node) or
+ *     NULL (no Dirichlet nodes, e.g. BP1/BP2 with Neumann conditions).
+ *   flags: 0 or BP_SETUP_FP32.
+ *   stream: stream for the uploads; bp_setup synchronises it before return.
+ * Errors: BP_ERR_ARG (ranges), BP_ERR_MESH (Jacobian <= 0 at a quadrature
+ * point -- the message names the element -- or an id out of range),
+ * BP_ERR_OOM, BP_ERR_HIP. On error *out is set to NULL.
+ */
+int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem,
+             int64_t nglobal, const int64_t *elem_dofs, const double *node_xyz,
+             const uint8_t *dirichlet, unsigned flags, void *stream);
+
+/* Sizes of an operator: nelem, nglobal, p, q, ncomp (any pointer may be NULL). */
+int bp_info(bp_op op, int64_t *nelem, int64_t *nglobal, int *p, int *q, int *ncomp);
+
+/*
+ * bp_set_coeff -- variable coefficient of the stiffness operator.
+ * Section 4, eq. (hm1)/(ip1): a(v,u) = int mu grad v . grad u with mu given at
+ * the quadrature points: the element operator of eq. (bk5x) uses mu_q G_q.
+ *   kappa_q: device double [nelem][q^3], read during the call (copied into a
+ *   library buffer as mu_q G_q); NULL restores mu = 1.
+ * Affects BP_STIFF in bp_apply, bp_diag and the solves; not bp_grad_kappa.
+ */
+int bp_set_coeff(bp_op op, const double *kappa_q, void *stream);
+
+/*
+ * bp_apply -- w = Q^T A_L Q u (BP_STIFF) or Q^T B_L Q u (BP_MASS).
+ * Section 4 (w = Q^T A_L Q u), section 5 eq. (bk5x) / eq. (mass); with
+ * BP_MASKED, w = mask * A (mask * u) as the Dirichlet restriction of
+ * Appendix A1 (Nek5000 ax).
+ *   prec = BP_FP64: u, w are double [nglobal][ncomp].
+ *   prec = BP_FP32: u, w are float; requires BP_SETUP_FP32.
+ *   w is overwritten (it must not alias u).
+ */
+int bp_apply(bp_op op, int which, int prec, const void *u, void *w,
+             unsigned flags, void *stream);
+
+/*
+ * bp_diag -- d = diag(Q^T A_L Q) (or of B), the Jacobi preconditioner's
+ * diagonal (section 3: diagonally preconditioned CG). d: device double
+ * [nglobal] (the same for every component). With BP_MASKED, d = 0 on
+ * Dirichlet nodes.
+ */
+int bp_diag(bp_op op, int which, double *d, unsigned flags, void *stream);
+
+/* Statistics of a solve (host struct filled on return). */
+typedef struct {
+  int iters;          /* CG iterations done (inner iterations for the mixed solve) */
+  int outer;          /* defect-correction steps (mixed solve), else 0               */
+  int converged;      /* 1 if every component reached rtol                          */
+  int ncomp;
+  double rel_res[8];  /* final ||r||_2 / ||b||_2 per component                       */
+  double ms;          /* device time of the iteration loop in milliseconds           */
+  double apply_ms;    /* with BP_OPT_TIME_APPLY: summed device time of the operator
+                         launches inside the loop (HIP events on the stream), else 0 */
+  int apply_count;    /* number of operator launches timed                          */
+  int pad_;
+} bp_pcg_stats;
+
+/*
+ * bp_pcg_solve -- Jacobi-preconditioned CG for which x = b (section 3).
+ * BP_STIFF solves the masked stiffness system (BP3-BP6; Dirichlet nodes stay
+ * 0); BP_MASS solves the unmasked mass system (BP1, BP2) -- if the operator
+ * was built with Dirichlet nodes the mass system is masked too.
+ *   b: device double [nglobal][ncomp]; x: device double, in: x0, out: solution.
+ *   fixed_iters != 0: exactly maxit iterations, no convergence test (the
+ *     timing mode of section 2); otherwise stop at the first iteration with
+ *     max_c ||r_c|| / ||b_c|| <= rtol, or at maxit (converged = 0, not an error).
+ *   st: may be NULL. Components use independent CG scalars. Entries of b on
+ *   Dirichlet nodes are ignored (read as 0).
+ * The call synchronises the stream before it returns.
+ * Errors: BP_ERR_NONFINITE if b holds NaN/Inf, BP_ERR_BREAKDOWN if p.Ap < 0.
+ */
+int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol,
+                 int maxit, int fixed_iters, bp_pcg_stats *st, void *stream);
+
+/*
+ * bp_pcg_solve_mixed -- FP64 defect correction around an FP32 Jacobi-PCG
+ * (stiffness only; needs BP_SETUP_FP32). Outer step: r = b - A x in FP64,
+ * stop when ||r||/||b|| <= outer_rtol; else solve A d = r in FP32 (vectors,
+ * geometric factors and operator in FP32, dot products accumulated in FP64)
+ * to inner_rtol or max_inner iterations, x += d in FP64.
+ * b, x: device double; synchronises the stream before return.
+ */
+int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
+                       double inner_rtol, int max_outer, int max_inner,
+                       bp_pcg_stats *st, void *stream);
+
+/*
+ * bp_grad_kappa -- g_q = - sum_c (D lam_c)_q^T G_q (D u_c)_q per element and
+ * quadrature point: the derivative of lam^T A(kappa) u with respect to the
+ * coefficient (section 4 eq. (ip1) with mu = kappa; section 5 eq. (bk5x)),
+ * summed over the ncomp components. lam, u: device double [nglobal][ncomp]
+ * (masked on Dirichlet nodes); g: device double [nelem][q^3], overwritten.
+ */
+int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
+                  void *stream);
+
+/*
+ * bp_set_option -- operator options (host state only, no device work).
+ *   BP_OPT_TIME_APPLY (value 0/1): bp_pcg_solve records a HIP event pair on
+ *   its stream around every operator launch of the iteration loop (at most
+ *   4096 pairs per solve) and reports their summed duration in
+ *   bp_pcg_stats.apply_ms. Costs two event records per iteration.
+ * Unknown options return BP_ERR_ARG.
+ */
+#define BP_OPT_TIME_APPLY 1
+int bp_set_option(bp_op op, int option, int value);
+
+/* Free every buffer of the operator (synchronises the device first). */
+int bp_destroy(bp_op op);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *bp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BP_H */

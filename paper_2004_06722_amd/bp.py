@@ -1,0 +1,161 @@
+"""Python binding of the bake-off library: argument marshalling only.
+
+Every computation runs in libbp.so's HIP kernels; torch supplies device
+memory (tensors) and the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (BP_FP32, BP_FP64, BP_MASKED, BP_MASS, BP_QUAD_GL, BP_QUAD_GLL,
+                   BP_SETUP_FP32, BP_STIFF, PcgStats, check)
+
+MASS, STIFF = BP_MASS, BP_STIFF
+GL, GLL = BP_QUAD_GL, BP_QUAD_GLL
+
+
+def rule(n: int, quad: int):
+    """The library's 1D rule: (points, weights) as numpy arrays."""
+    lib = _lib.load()
+    x = np.zeros(n)
+    w = np.zeros(n)
+    check(lib.bp_rule(n, quad, x.ctypes.data, w.ctypes.data))
+    return x, w
+
+
+def bp_quadrature(bp: int, p: int):
+    """(q, quad) that Table "bps" assigns to BPj at order p."""
+    if bp in (1, 2, 3, 4):
+        return p + 2, GL
+    if bp in (5, 6):
+        return p + 1, GLL
+    raise ValueError(bp)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """A mesh + order + quadrature on the current HIP device (bp_setup)."""
+
+    def __init__(self, p: int, q: int, quad: int, elem_dofs, node_xyz, nglobal: int,
+                 dirichlet=None, ncomp: int = 1, fp32: bool = False):
+        self._lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        ed = np.ascontiguousarray(elem_dofs, dtype=np.int64)
+        xyz = np.ascontiguousarray(node_xyz, dtype=np.float64)
+        p1 = p + 1
+        if ed.ndim != 2 or ed.shape[1] != p1 ** 3:
+            raise ValueError("elem_dofs must be [nelem, (p+1)^3]")
+        if xyz.shape != (ed.shape[0], p1 ** 3, 3):
+            raise ValueError("node_xyz must be [nelem, (p+1)^3, 3]")
+        dr = None
+        if dirichlet is not None:
+            dr = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+            if dr.shape != (nglobal,):
+                raise ValueError("dirichlet must be [nglobal]")
+        self.p, self.q, self.quad, self.ncomp = p, q, quad, ncomp
+        self.nelem, self.nglobal = ed.shape[0], int(nglobal)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        check(self._lib.bp_setup(ctypes.byref(h), p, q, quad, ncomp, self.nelem, self.nglobal,
+                                 ed.ctypes.data, xyz.ctypes.data,
+                                 None if dr is None else dr.ctypes.data,
+                                 BP_SETUP_FP32 if fp32 else 0, _stream()))
+        self._h = h
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize()
+            self._lib.bp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def _vec(self, t: torch.Tensor, dtype=torch.float64, name="vector") -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}")
+        if t.numel() != self.nglobal * self.ncomp or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with nglobal*ncomp entries")
+        return t
+
+    def new_vector(self, dtype=torch.float64) -> torch.Tensor:
+        shape = (self.nglobal,) if self.ncomp == 1 else (self.nglobal, self.ncomp)
+        return torch.zeros(shape, dtype=dtype, device=self.device)
+
+    def apply(self, which: int, u: torch.Tensor, out: torch.Tensor | None = None,
+              masked: bool = True) -> torch.Tensor:
+        """w = [mask] Q^T A_L Q [mask] u (bp_apply); FP32 if u is float32."""
+        prec = BP_FP32 if u.dtype == torch.float32 else BP_FP64
+        self._vec(u, u.dtype, "u")
+        w = torch.empty_like(u) if out is None else self._vec(out, u.dtype, "out")
+        check(self._lib.bp_apply(self._h, which, prec, _ptr(u), _ptr(w),
+                                 BP_MASKED if masked else 0, _stream()))
+        return w
+
+    def diag(self, which: int, masked: bool = True) -> torch.Tensor:
+        d = torch.empty(self.nglobal, dtype=torch.float64, device=self.device)
+        check(self._lib.bp_diag(self._h, which, _ptr(d), BP_MASKED if masked else 0, _stream()))
+        return d
+
+    def set_option(self, option: int, value: int):
+        check(self._lib.bp_set_option(self._h, option, value))
+
+    def set_coeff(self, kappa: torch.Tensor | None):
+        if kappa is not None:
+            if kappa.dtype != torch.float64 or kappa.device.type != "cuda" or \
+                    kappa.numel() != self.nelem * self.q ** 3 or not kappa.is_contiguous():
+                raise ValueError("kappa must be a contiguous float64 device tensor [nelem, q^3]")
+        check(self._lib.bp_set_coeff(self._h, _ptr(kappa), _stream()))
+
+    def pcg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, which: int = STIFF,
+                  rtol: float = 1e-8, maxit: int = 1000, fixed_iters: bool = False):
+        """Jacobi-PCG (bp_pcg_solve). Returns (x, stats dict)."""
+        self._vec(b, name="b")
+        x = torch.zeros_like(b) if x is None else self._vec(x, name="x")
+        st = PcgStats()
+        check(self._lib.bp_pcg_solve(self._h, which, _ptr(b), _ptr(x), float(rtol), int(maxit),
+                                     1 if fixed_iters else 0, ctypes.byref(st), _stream()))
+        return x, st.as_dict()
+
+    def pcg_solve_mixed(self, b: torch.Tensor, x: torch.Tensor | None = None,
+                        outer_rtol: float = 1e-10, inner_rtol: float = 1e-5,
+                        max_outer: int = 50, max_inner: int = 2000):
+        self._vec(b, name="b")
+        x = torch.zeros_like(b) if x is None else self._vec(x, name="x")
+        st = PcgStats()
+        check(self._lib.bp_pcg_solve_mixed(self._h, _ptr(b), _ptr(x), float(outer_rtol),
+                                           float(inner_rtol), int(max_outer), int(max_inner),
+                                           ctypes.byref(st), _stream()))
+        return x, st.as_dict()
+
+    def grad_kappa(self, lam: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+        self._vec(lam, name="lam")
+        self._vec(u, name="u")
+        g = torch.empty((self.nelem, self.q ** 3), dtype=torch.float64, device=self.device)
+        check(self._lib.bp_grad_kappa(self._h, _ptr(lam), _ptr(u), _ptr(g), _stream()))
+        return g

@@ -1,0 +1,92 @@
+// Internal declarations of the bake-off library (host side).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/bp.h"
+
+namespace bp {
+
+// ---- errors ---------------------------------------------------------------
+int set_error(int code, const std::string &msg);
+#define BP_HIP(call)                                                         \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::bp::set_error(BP_ERR_HIP, std::string(#call) + ": " +         \
+                                             hipGetErrorString(e_));         \
+  } while (0)
+
+// ---- host setup (setup.cpp) ----------------------------------------------
+// 1D rules on [-1, 1], ascending.
+void gll_rule(int n, double *x, double *w);
+void gl_rule(int n, double *x, double *w);
+// Lagrange basis on `nodes` (n) evaluated / differentiated at `pts` (m):
+// out[a*n + j] = h_j(pts[a]) or h_j'(pts[a]) (barycentric form).
+void lagrange_interp(int n, const double *nodes, int m, const double *pts, double *out);
+void lagrange_deriv(int n, const double *nodes, int m, const double *pts, double *out);
+
+// Per-operator 1D data: nodes, quadrature, J (q x p1), D (q x p1), Dq (q x q).
+struct Basis {
+  int p1 = 0, q = 0;
+  bool colloc = false;
+  std::vector<double> xi, eta, rho, J, D, Dq;
+};
+Basis make_basis(int p, int q, int quad);
+
+// Geometric factors of eq. (gij) and B~ of eq. (mass) for every element,
+// computed with `nthreads` host threads. G [E][6][q^3], Bt [E][q^3].
+// Returns -1 on success, else the first element with Jacobian <= 0 (or
+// non-finite) at some quadrature point.
+int64_t geometric_factors(const Basis &b, int64_t nelem, const double *node_xyz,
+                          double *G, double *Bt, int nthreads);
+
+// ---- device-side scalars of the CG iteration --------------------------------
+constexpr int kMaxComp = 8;
+constexpr int kMaxTimedApplies = 4096;
+struct DevScalars {
+  double rz[kMaxComp], pap[kMaxComp], rr[kMaxComp], bb[kMaxComp];
+  double alpha[kMaxComp], beta[kMaxComp];
+  double tol2;
+  int done;       // set when every component meets the tolerance
+  int iters;      // iterations performed while not done
+  int breakdown;  // p.Ap < 0 seen
+  int nonfinite;  // NaN/Inf in a reduction
+  int fixed;      // fixed-iteration mode: never set done
+  int pad_[3];
+};
+
+}  // namespace bp
+
+// The operator object.
+struct bp_op_s {
+  int p = 0, p1 = 0, q = 0, quad = 0, ncomp = 1;
+  int64_t nelem = 0, nglobal = 0;
+  bool colloc = false, has_dirichlet = false, fp32 = false;
+  int device = 0;
+  bp::Basis basis;
+  // device buffers (owned)
+  int32_t *idx = nullptr;    // [E][p1^3]; Dirichlet node g stored as -1-g
+  double *G = nullptr;       // [E][6][q^3] geometric factors
+  double *Gk = nullptr;      // kappa_q * G (allocated by bp_set_coeff)
+  double *Bt = nullptr;      // [E][q^3]
+  double *basis_d = nullptr; // J | D | Dq on the device (FP64)
+  float *G32 = nullptr, *Gk32 = nullptr, *Bt32 = nullptr, *basis32 = nullptr;
+  bool kappa_set = false;
+  double *dinv[2] = {nullptr, nullptr};  // [0] mass, [1] stiffness (masked)
+  bool dinv_valid[2] = {false, false};
+  // CG workspace
+  double *r = nullptr, *pv = nullptr, *w = nullptr, *part = nullptr, *tmp = nullptr;
+  float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr, *x32 = nullptr, *b32 = nullptr;
+  float *dinv32 = nullptr;
+  int64_t part_len = 0;      // doubles in `part`
+  bp::DevScalars *sc = nullptr;   // device
+  bp::DevScalars *sc_host = nullptr;  // pinned host mirror
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool time_apply = false;
+  std::vector<hipEvent_t> apply_ev;  // pairs around operator launches
+};

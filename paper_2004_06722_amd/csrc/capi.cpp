@@ -1,0 +1,564 @@
+// C ABI of the bake-off library: operator setup, application, diagonal and
+// the Jacobi-PCG drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "bp_internal.h"
+#include "launch.h"
+
+namespace bp {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+namespace {
+
+template <typename T>
+int dmalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return set_error(BP_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                     " bytes failed: " + hipGetErrorString(e));
+  }
+  return BP_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+void release(bp_op op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  dfree(op->idx);
+  dfree(op->G);
+  dfree(op->Gk);
+  dfree(op->Bt);
+  dfree(op->basis_d);
+  dfree(op->G32);
+  dfree(op->Gk32);
+  dfree(op->Bt32);
+  dfree(op->basis32);
+  dfree(op->dinv[0]);
+  dfree(op->dinv[1]);
+  dfree(op->r);
+  dfree(op->pv);
+  dfree(op->w);
+  dfree(op->part);
+  dfree(op->tmp);
+  dfree(op->r32);
+  dfree(op->p32);
+  dfree(op->w32);
+  dfree(op->x32);
+  dfree(op->dinv32);
+  dfree(op->b32);
+  dfree(op->sc);
+  if (op->sc_host) (void)hipHostFree(op->sc_host);
+  if (op->ev0) (void)hipEventDestroy(op->ev0);
+  if (op->ev1) (void)hipEventDestroy(op->ev1);
+  for (auto ev : op->apply_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  delete op;
+}
+
+int host_threads() {
+  unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(h, 32u));
+}
+
+// Upload basis J | D | Dq (FP64 and optional FP32 copies).
+int upload_basis(bp_op op, hipStream_t s) {
+  const Basis &b = op->basis;
+  std::vector<double> all;
+  all.insert(all.end(), b.J.begin(), b.J.end());
+  all.insert(all.end(), b.D.begin(), b.D.end());
+  all.insert(all.end(), b.Dq.begin(), b.Dq.end());
+  int rc = dmalloc(&op->basis_d, all.size());
+  if (rc) return rc;
+  BP_HIP(hipMemcpyAsync(op->basis_d, all.data(), all.size() * sizeof(double),
+                        hipMemcpyHostToDevice, s));
+  BP_HIP(hipStreamSynchronize(s));
+  if (op->fp32) {
+    std::vector<float> f(all.begin(), all.end());
+    rc = dmalloc(&op->basis32, f.size());
+    if (rc) return rc;
+    BP_HIP(hipMemcpyAsync(op->basis32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice,
+                          s));
+    BP_HIP(hipStreamSynchronize(s));
+  }
+  return BP_OK;
+}
+
+int check_op(bp_op op) {
+  if (!op) return set_error(BP_ERR_ARG, "null operator");
+  int dev = -1;
+  BP_HIP(hipGetDevice(&dev));
+  if (dev != op->device)
+    return set_error(BP_ERR_ARG, "operator lives on device " + std::to_string(op->device) +
+                                     ", current device is " + std::to_string(dev));
+  return BP_OK;
+}
+
+// Inverse diagonal for `which` (cached; masked when the operator has Dirichlet nodes).
+int ensure_dinv(bp_op op, int which, hipStream_t s) {
+  const int slot = which == BP_STIFF ? 1 : 0;
+  if (op->dinv_valid[slot]) return BP_OK;
+  if (!op->dinv[slot]) {
+    int rc = dmalloc(&op->dinv[slot], op->nglobal);
+    if (rc) return rc;
+  }
+  fill_f64(op->tmp, op->nglobal, 0.0, s);
+  int rc = launch_diag(op, which, op->tmp, op->has_dirichlet, s);
+  if (rc) return rc;
+  invert_diag(op->tmp, op->dinv[slot], (slot == 1 && op->fp32) ? op->dinv32 : nullptr,
+              op->nglobal, s);
+  BP_HIP(hipGetLastError());
+  op->dinv_valid[slot] = true;
+  return BP_OK;
+}
+
+int upload_scalars(bp_op op, double rtol, bool fixed, hipStream_t s) {
+  std::memset(op->sc_host, 0, sizeof(DevScalars));
+  op->sc_host->tol2 = rtol * rtol;
+  op->sc_host->fixed = fixed ? 1 : 0;
+  BP_HIP(hipMemcpyAsync(op->sc, op->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+  return BP_OK;
+}
+
+int download_scalars(bp_op op, hipStream_t s) {
+  BP_HIP(hipMemcpyAsync(op->sc_host, op->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  BP_HIP(hipStreamSynchronize(s));
+  return BP_OK;
+}
+
+// Jacobi-PCG on precision T. x0_zero: x is zero on entry (skips A x0).
+template <typename T>
+int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r, T *p, T *w,
+            double rtol, int maxit, bool fixed, bool x0_zero, hipStream_t s, int *iters_out,
+            float *ms_out, double *apply_ms_out = nullptr, int *apply_count_out = nullptr) {
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal, nv = n * nc;
+  const bool masked = op->has_dirichlet;
+  const int64_t nb_apply = apply_blocks(op), nb_vec = vec_blocks(n);
+  int rc = upload_scalars(op, rtol, fixed, s);
+  if (rc) return rc;
+  if constexpr (sizeof(T) == 8)
+    fill_f64((double *)w, nv, 0.0, s);
+  else
+    fill_f32((float *)w, nv, 0.0f, s);
+  if (!x0_zero) {
+    rc = launch_apply(op, which, f32, x, w, masked, nullptr, nullptr, s);
+    if (rc) return rc;
+  }
+  cg_init<T>(nc, n, b, r, w, p, dinv, op->part, op->sc, s);
+  BP_HIP(hipGetLastError());
+  BP_HIP(hipEventRecord(op->ev0, s));
+  const int poll = 8;
+  int it = 0, timed = 0;
+  const int *done = &op->sc->done;
+  if (op->time_apply && op->apply_ev.empty()) {
+    op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
+    for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
+  }
+  while (it < maxit) {
+    const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
+    for (int c = 0; c < chunk; ++c) {
+      const bool tm = op->time_apply && timed < kMaxTimedApplies;
+      if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
+      rc = launch_apply(op, which, f32, p, w, masked, op->part, done, s);
+      if (rc) return rc;
+      if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
+      cg_fin_alpha(nc, op->part, nb_apply, op->sc, s);
+      cg_update_xr<T>(nc, n, x, p, r, w, dinv, op->part, op->sc, s);
+      cg_fin_beta(nc, nb_vec, op->part, op->sc, s);
+      cg_update_p<T>(nc, n, p, r, dinv, op->sc, s);
+    }
+    BP_HIP(hipGetLastError());
+    it += chunk;
+    if (!fixed) {
+      rc = download_scalars(op, s);
+      if (rc) return rc;
+      if (op->sc_host->done) break;
+    }
+  }
+  BP_HIP(hipEventRecord(op->ev1, s));
+  rc = download_scalars(op, s);
+  if (rc) return rc;
+  float ms = 0.0f;
+  BP_HIP(hipEventElapsedTime(&ms, op->ev0, op->ev1));
+  if (ms_out) *ms_out = ms;
+  if (iters_out) *iters_out = op->sc_host->iters;
+  if (apply_ms_out) {
+    double sum = 0.0;
+    for (int k = 0; k < timed; ++k) {
+      float t = 0.0f;
+      BP_HIP(hipEventElapsedTime(&t, op->apply_ev[2 * k], op->apply_ev[2 * k + 1]));
+      sum += t;
+    }
+    *apply_ms_out = sum;
+    if (apply_count_out) *apply_count_out = timed;
+  }
+  if (op->sc_host->nonfinite) return set_error(BP_ERR_NONFINITE, "non-finite value in CG reductions");
+  if (op->sc_host->breakdown) return set_error(BP_ERR_BREAKDOWN, "CG breakdown: p.Ap < 0");
+  return BP_OK;
+}
+
+void fill_stats(bp_op op, double rtol, bp_pcg_stats *st) {
+  if (!st) return;
+  st->ncomp = op->ncomp;
+  bool conv = true;
+  for (int c = 0; c < kMaxComp; ++c) st->rel_res[c] = 0.0;
+  for (int c = 0; c < op->ncomp; ++c) {
+    const double bb = op->sc_host->bb[c] > 0 ? op->sc_host->bb[c] : 1.0;
+    st->rel_res[c] = std::sqrt(std::max(0.0, op->sc_host->rr[c]) / bb);
+    conv = conv && st->rel_res[c] <= rtol;
+  }
+  st->converged = conv ? 1 : 0;
+}
+
+}  // namespace
+}  // namespace bp
+
+using namespace bp;
+
+extern "C" {
+
+int bp_version(void) { return 100; }
+
+const char *bp_last_error(void) { return g_last_error.c_str(); }
+
+int bp_rule(int n, int quad, double *x, double *w) {
+  if (!x) return set_error(BP_ERR_ARG, "bp_rule: x is NULL");
+  if (quad == BP_QUAD_GLL) {
+    if (n < 2 || n > 64) return set_error(BP_ERR_ARG, "bp_rule: GLL needs 2 <= n <= 64");
+    gll_rule(n, x, w);
+  } else if (quad == BP_QUAD_GL) {
+    if (n < 1 || n > 64) return set_error(BP_ERR_ARG, "bp_rule: GL needs 1 <= n <= 64");
+    gl_rule(n, x, w);
+  } else {
+    return set_error(BP_ERR_ARG, "bp_rule: unknown quadrature");
+  }
+  return BP_OK;
+}
+
+int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64_t nglobal,
+             const int64_t *elem_dofs, const double *node_xyz, const uint8_t *dirichlet,
+             unsigned flags, void *stream) {
+  if (!out) return set_error(BP_ERR_ARG, "bp_setup: out is NULL");
+  *out = nullptr;
+  if (p < 1 || p > 15) return set_error(BP_ERR_ARG, "bp_setup: p must be in [1, 15]");
+  if (q < 2 || q > 16) return set_error(BP_ERR_ARG, "bp_setup: q must be in [2, 16]");
+  if (quad != BP_QUAD_GL && quad != BP_QUAD_GLL)
+    return set_error(BP_ERR_ARG, "bp_setup: unknown quadrature");
+  if (quad == BP_QUAD_GLL && q != p + 1)
+    return set_error(BP_ERR_ARG, "bp_setup: GLL quadrature must be collocated (q = p + 1)");
+  if (ncomp < 1 || ncomp > kMaxComp) return set_error(BP_ERR_ARG, "bp_setup: ncomp must be in [1, 8]");
+  if (nelem < 1) return set_error(BP_ERR_ARG, "bp_setup: nelem must be >= 1");
+  if (nglobal < 1 || nglobal > 2147483647LL)
+    return set_error(BP_ERR_ARG, "bp_setup: nglobal must be in [1, 2^31 - 1]");
+  if (!elem_dofs || !node_xyz) return set_error(BP_ERR_ARG, "bp_setup: NULL mesh array");
+  if (flags & ~BP_SETUP_FP32) return set_error(BP_ERR_ARG, "bp_setup: unknown flag");
+  if (!kernels_cover(p, q, quad))
+    return set_error(BP_ERR_ARG, "bp_setup: no compiled kernels for p=" + std::to_string(p) +
+                                     ", q=" + std::to_string(q) +
+                                     " (compiled: p <= 8 with GLL q=p+1 or GL q=p+2)");
+  hipStream_t s = (hipStream_t)stream;
+  const int p1 = p + 1;
+  const int64_t n3 = (int64_t)p1 * p1 * p1, nq = (int64_t)q * q * q;
+
+  // gather map with the Dirichlet sign encoding
+  std::vector<int32_t> idx((size_t)(nelem * n3));
+  for (int64_t k = 0; k < nelem * n3; ++k) {
+    const int64_t g = elem_dofs[k];
+    if (g < 0 || g >= nglobal)
+      return set_error(BP_ERR_MESH, "bp_setup: elem_dofs entry " + std::to_string(k) + " = " +
+                                        std::to_string(g) + " out of range (element " +
+                                        std::to_string(k / n3) + ")");
+    const bool dir = dirichlet && dirichlet[g];
+    idx[k] = dir ? (int32_t)(-1 - g) : (int32_t)g;
+  }
+
+  bp_op op = new bp_op_s();
+  op->p = p;
+  op->p1 = p1;
+  op->q = q;
+  op->quad = quad;
+  op->ncomp = ncomp;
+  op->nelem = nelem;
+  op->nglobal = nglobal;
+  op->fp32 = (flags & BP_SETUP_FP32) != 0;
+  op->has_dirichlet = dirichlet != nullptr;
+  op->basis = make_basis(p, q, quad);
+  op->colloc = op->basis.colloc;
+  if (hipGetDevice(&op->device) != hipSuccess) {
+    release(op);
+    return set_error(BP_ERR_HIP, "bp_setup: no HIP device");
+  }
+
+  // geometric factors on the host
+  std::vector<double> G((size_t)(nelem * 6 * nq)), Bt((size_t)(nelem * nq));
+  const int64_t bad = geometric_factors(op->basis, nelem, node_xyz, G.data(), Bt.data(),
+                                        host_threads());
+  if (bad >= 0) {
+    release(op);
+    return set_error(BP_ERR_MESH, "bp_setup: non-positive Jacobian in element " +
+                                      std::to_string(bad));
+  }
+
+  int rc = BP_OK;
+#define TRY(x)          \
+  do {                  \
+    rc = (x);           \
+    if (rc) {           \
+      release(op);      \
+      return rc;        \
+    }                   \
+  } while (0)
+#define TRYHIP(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      release(op);                                                                  \
+      return set_error(BP_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    }                                                                               \
+  } while (0)
+
+  const int64_t nv = nglobal * ncomp;
+  TRY(dmalloc(&op->idx, idx.size()));
+  TRY(dmalloc(&op->G, G.size()));
+  TRY(dmalloc(&op->Bt, Bt.size()));
+  TRYHIP(hipMemcpyAsync(op->idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  TRYHIP(hipMemcpyAsync(op->G, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  TRYHIP(hipMemcpyAsync(op->Bt, Bt.data(), Bt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  TRYHIP(hipStreamSynchronize(s));
+  TRY(upload_basis(op, s));
+  TRY(dmalloc(&op->r, nv));
+  TRY(dmalloc(&op->pv, nv));
+  TRY(dmalloc(&op->w, nv));
+  TRY(dmalloc(&op->tmp, std::max<int64_t>(nv, nglobal)));
+  op->part_len = std::max<int64_t>(apply_blocks(op) * ncomp, kVecMaxBlocks * 3 * ncomp);
+  TRY(dmalloc(&op->part, op->part_len));
+  TRY(dmalloc(&op->sc, 1));
+  TRYHIP(hipHostMalloc((void **)&op->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  TRYHIP(hipEventCreate(&op->ev0));
+  TRYHIP(hipEventCreate(&op->ev1));
+  if (op->fp32) {
+    std::vector<float> f(G.begin(), G.end());
+    TRY(dmalloc(&op->G32, f.size()));
+    TRYHIP(hipMemcpyAsync(op->G32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    TRYHIP(hipStreamSynchronize(s));
+    std::vector<float> fb(Bt.begin(), Bt.end());
+    TRY(dmalloc(&op->Bt32, fb.size()));
+    TRYHIP(hipMemcpyAsync(op->Bt32, fb.data(), fb.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    TRYHIP(hipStreamSynchronize(s));
+    TRY(dmalloc(&op->r32, nv));
+    TRY(dmalloc(&op->p32, nv));
+    TRY(dmalloc(&op->w32, nv));
+    TRY(dmalloc(&op->x32, nv));
+    TRY(dmalloc(&op->b32, nv));
+    TRY(dmalloc(&op->dinv32, nglobal));
+  }
+#undef TRY
+#undef TRYHIP
+  *out = op;
+  return BP_OK;
+}
+
+int bp_info(bp_op op, int64_t *nelem, int64_t *nglobal, int *p, int *q, int *ncomp) {
+  if (!op) return set_error(BP_ERR_ARG, "null operator");
+  if (nelem) *nelem = op->nelem;
+  if (nglobal) *nglobal = op->nglobal;
+  if (p) *p = op->p;
+  if (q) *q = op->q;
+  if (ncomp) *ncomp = op->ncomp;
+  return BP_OK;
+}
+
+int bp_set_coeff(bp_op op, const double *kappa_q, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int nq = op->q * op->q * op->q;
+  if (!kappa_q) {
+    op->kappa_set = false;
+  } else {
+    if (!op->Gk) {
+      rc = dmalloc(&op->Gk, (size_t)op->nelem * 6 * nq);
+      if (rc) return rc;
+      if (op->fp32) {
+        rc = dmalloc(&op->Gk32, (size_t)op->nelem * 6 * nq);
+        if (rc) return rc;
+      }
+    }
+    scale_geometry(op->G, kappa_q, op->Gk, op->Gk32, op->nelem, nq, s);
+    BP_HIP(hipGetLastError());
+    op->kappa_set = true;
+  }
+  op->dinv_valid[1] = false;
+  return BP_OK;
+}
+
+int bp_apply(bp_op op, int which, int prec, const void *u, void *w, unsigned flags,
+             void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_apply: which");
+  if (prec != BP_FP64 && prec != BP_FP32) return set_error(BP_ERR_ARG, "bp_apply: prec");
+  if (prec == BP_FP32 && !op->fp32)
+    return set_error(BP_ERR_ARG, "bp_apply: FP32 needs BP_SETUP_FP32");
+  if (!u || !w) return set_error(BP_ERR_ARG, "bp_apply: NULL vector");
+  if (u == w) return set_error(BP_ERR_ARG, "bp_apply: w must not alias u");
+  if (flags & ~BP_MASKED) return set_error(BP_ERR_ARG, "bp_apply: unknown flag");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nv = op->nglobal * op->ncomp;
+  if (prec == BP_FP32)
+    fill_f32((float *)w, nv, 0.0f, s);
+  else
+    fill_f64((double *)w, nv, 0.0, s);
+  return launch_apply(op, which, prec == BP_FP32, u, w, (flags & BP_MASKED) != 0, nullptr,
+                      nullptr, s);
+}
+
+int bp_diag(bp_op op, int which, double *d, unsigned flags, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_diag: which");
+  if (!d) return set_error(BP_ERR_ARG, "bp_diag: NULL output");
+  if (flags & ~BP_MASKED) return set_error(BP_ERR_ARG, "bp_diag: unknown flag");
+  hipStream_t s = (hipStream_t)stream;
+  fill_f64(d, op->nglobal, 0.0, s);
+  return launch_diag(op, which, d, (flags & BP_MASKED) != 0, s);
+}
+
+int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, int maxit,
+                 int fixed_iters, bp_pcg_stats *st, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_pcg_solve: which");
+  if (!b || !x) return set_error(BP_ERR_ARG, "bp_pcg_solve: NULL vector");
+  if (maxit < 0 || !(rtol >= 0.0)) return set_error(BP_ERR_ARG, "bp_pcg_solve: maxit/rtol");
+  hipStream_t s = (hipStream_t)stream;
+  rc = ensure_dinv(op, which, s);
+  if (rc) return rc;
+  int iters = 0;
+  float ms = 0.0f;
+  double apply_ms = 0.0;
+  int apply_count = 0;
+  rc = pcg_run<double>(op, which, false, b, x, op->dinv[which == BP_STIFF ? 1 : 0], op->r, op->pv,
+                       op->w, rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
+                       &apply_count);
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->iters = iters;
+    st->ms = ms;
+    st->apply_ms = apply_ms;
+    st->apply_count = apply_count;
+    fill_stats(op, rtol, st);
+  }
+  return rc;
+}
+
+int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
+                       double inner_rtol, int max_outer, int max_inner, bp_pcg_stats *st,
+                       void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!op->fp32) return set_error(BP_ERR_ARG, "bp_pcg_solve_mixed: needs BP_SETUP_FP32");
+  if (!b || !x) return set_error(BP_ERR_ARG, "bp_pcg_solve_mixed: NULL vector");
+  if (max_outer < 0 || max_inner < 1 || !(outer_rtol >= 0) || !(inner_rtol >= 0))
+    return set_error(BP_ERR_ARG, "bp_pcg_solve_mixed: bad limits");
+  hipStream_t s = (hipStream_t)stream;
+  rc = ensure_dinv(op, BP_STIFF, s);
+  if (rc) return rc;
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal, nv = n * nc;
+  const bool masked = op->has_dirichlet;
+  hipEvent_t t0, t1;
+  BP_HIP(hipEventCreate(&t0));
+  BP_HIP(hipEventCreate(&t1));
+  BP_HIP(hipEventRecord(t0, s));
+  int outer = 0, inner_total = 0;
+  for (;;) {
+    fill_f64(op->w, nv, 0.0, s);
+    rc = launch_apply(op, BP_STIFF, false, x, op->w, masked, nullptr, nullptr, s);
+    if (rc) break;
+    dc_residual(nc, n, b, op->r, op->w, op->part, op->sc, s);
+    rc = download_scalars(op, s);
+    if (rc) break;
+    double worst = 0.0;
+    bool bad = false;
+    for (int c = 0; c < nc; ++c) {
+      const double bb = op->sc_host->bb[c] > 0 ? op->sc_host->bb[c] : 1.0;
+      const double rel = std::sqrt(op->sc_host->rr[c] / bb);
+      bad = bad || !std::isfinite(rel);
+      worst = std::max(worst, rel);
+    }
+    if (bad) {
+      rc = set_error(BP_ERR_NONFINITE, "bp_pcg_solve_mixed: non-finite residual");
+      break;
+    }
+    if (worst <= outer_rtol || outer >= max_outer) break;
+    to_f32(op->r, op->b32, nv, s);
+    fill_f32(op->x32, nv, 0.0f, s);
+    int it = 0;
+    rc = pcg_run<float>(op, BP_STIFF, true, op->b32, op->x32, op->dinv32, op->r32, op->p32,
+                        op->w32, inner_rtol, max_inner, false, true, s, &it, nullptr);
+    if (rc) break;
+    inner_total += it;
+    dc_accumulate(nv, x, op->x32, s);
+    ++outer;
+  }
+  BP_HIP(hipEventRecord(t1, s));
+  BP_HIP(hipEventSynchronize(t1));
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, t0, t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->iters = inner_total;
+    st->outer = outer;
+    st->ms = ms;
+    fill_stats(op, outer_rtol, st);
+  }
+  return rc;
+}
+
+int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!lam || !u || !g) return set_error(BP_ERR_ARG, "bp_grad_kappa: NULL pointer");
+  return launch_grad_kappa(op, lam, u, g, (hipStream_t)stream);
+}
+
+int bp_set_option(bp_op op, int option, int value) {
+  if (!op) return set_error(BP_ERR_ARG, "null operator");
+  if (option == BP_OPT_TIME_APPLY) {
+    op->time_apply = value != 0;
+    return BP_OK;
+  }
+  return set_error(BP_ERR_ARG, "bp_set_option: unknown option " + std::to_string(option));
+}
+
+int bp_destroy(bp_op op) {
+  if (!op) return BP_OK;
+  release(op);
+  return BP_OK;
+}
+
+}  // extern "C"

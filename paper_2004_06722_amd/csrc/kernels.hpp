@@ -1,0 +1,520 @@
+// Device kernels of the bake-off operators (gfx950, wave64).
+//
+// Operator application w = Q^T A_L Q u (section 4) with the element operator
+// of section 5: eq. (bk5x) for the stiffness matrix and eq. (mass) for the
+// mass matrix, applied by sum factorisation (eq. (tens1)). One work-group
+// owns one element (or, for small p, a slab of elements); each thread owns
+// one (i, j) column of the element and walks the k direction in registers,
+// so the k-derivatives never leave the thread while the i- and
+// j-derivatives are taken through LDS tiles. The scatter w = Q^T w_L uses
+// hardware FP64/FP32 atomic adds into a zeroed w; the local energy
+// sum_e u_L^T w_L (Appendix A1: rho = w^T u before assembly) is reduced per
+// work-group into a partial sum.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace bp {
+
+// Thread plane of an element: M x M threads, M = max(p1, q); EPB elements per
+// work-group so that small orders still fill a wave; THREADS rounded up to
+// whole waves (idle lanes take part in barriers and reductions only).
+template <int P1, int Q>
+struct Plane {
+  static constexpr int M = P1 > Q ? P1 : Q;
+  static constexpr int N = M * M;
+  static constexpr int EPB = N >= 64 ? 1 : 64 / N;
+  static constexpr int USED = EPB * N;
+  static constexpr int THREADS = ((USED + 63) / 64) * 64;
+};
+
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// Sum v over the work-group in a fixed order; thread 0 stores out[c * stride].
+template <int NC, int THREADS>
+__device__ __forceinline__ void block_sum_store(double (&v)[NC], double *out, int stride) {
+  constexpr int NW = THREADS / 64;
+  __shared__ double red[NW][NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    v[c] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[wid][c] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < NW; ++k) s += red[k][c];
+      out[c * stride] = s;
+    }
+}
+
+// Decoded gather index: global id, or -1 when the node is skipped
+// (element slot not live, or a Dirichlet node under the mask).
+__device__ __forceinline__ int decode_index(int v, bool live, int masked) {
+  if (!live) return -1;
+  if (v >= 0) return v;
+  return masked ? -1 : -1 - v;
+}
+
+// ---------------------------------------------------------------------------
+// BK5/BK6: stiffness with collocated GLL quadrature (J^ = I, q = p1).
+// NC components share every load of G and of the gather map.
+// ---------------------------------------------------------------------------
+template <int P1, int NC, typename T>
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
+    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp,
+    int c0, int masked, double *__restrict__ part, const int *__restrict__ done) {
+  using PL = Plane<P1, P1>;
+  constexpr int N3 = P1 * P1 * P1, PAD = P1 + 1;
+  if (done && *done) return;
+  __shared__ T sD[P1][P1];
+  __shared__ T su[PL::EPB][NC][P1][P1][PAD];
+  __shared__ T sr[PL::EPB][NC][P1][P1][PAD];
+  __shared__ T ss[PL::EPB][NC][P1][P1][PAD];
+  const int t = threadIdx.x;
+  const bool act = t < PL::USED;
+  const int slot = act ? t / PL::N : 0;
+  const int ij = t % PL::N;
+  const int i = ij % P1, j = ij / P1;
+  const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
+  const bool live = act && e < nelem;
+  for (int x = t; x < P1 * P1; x += PL::THREADS) sD[x / P1][x % P1] = basis[P1 * P1 + x];
+
+  T ru[NC][P1];
+  int gk[P1];
+#pragma unroll
+  for (int k = 0; k < P1; ++k) {
+    const int l = i + P1 * (j + P1 * k);
+    const int v = live ? __builtin_nontemporal_load(idx + e * N3 + l) : -1;
+    gk[k] = decode_index(v, live, masked);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T val = gk[k] >= 0 ? u[(int64_t)gk[k] * ncomp + c0 + c] : T(0);
+      ru[c][k] = val;
+      if (act) su[slot][c][k][j][i] = val;
+    }
+  }
+  __syncthreads();
+
+  // derivative along t (k): thread-local
+  T rt[NC][P1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) s += sD[k][m] * ru[c][m];
+      rt[c][k] = s;
+    }
+
+  // derivatives along r, s through LDS; apply G (6 symmetric components)
+  const T *Ge = G + (live ? e : 0) * 6 * N3 + ij;
+#pragma unroll
+  for (int k = 0; k < P1; ++k) {
+    T g[6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n)
+      g[n] = live ? __builtin_nontemporal_load(Ge + n * N3 + k * P1 * P1) : T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T ur = 0, us = 0;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) {
+        ur += sD[i][m] * su[slot][c][k][j][m];
+        us += sD[j][m] * su[slot][c][k][m][i];
+      }
+      const T ut = rt[c][k];
+      const T vr = g[0] * ur + g[1] * us + g[2] * ut;
+      const T vs = g[1] * ur + g[3] * us + g[4] * ut;
+      const T vt = g[2] * ur + g[4] * us + g[5] * ut;
+      if (act) {
+        sr[slot][c][k][j][i] = vr;
+        ss[slot][c][k][j][i] = vs;
+      }
+      rt[c][k] = vt;
+    }
+  }
+  __syncthreads();
+
+  // transposed derivatives, energy and scatter
+  double en[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) en[c] = 0.0;
+#pragma unroll
+  for (int k = 0; k < P1; ++k) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T acc = 0;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) {
+        acc += sD[m][k] * rt[c][m];
+        acc += sD[m][i] * sr[slot][c][k][j][m];
+        acc += sD[m][j] * ss[slot][c][k][m][i];
+      }
+      en[c] += (double)ru[c][k] * (double)acc;
+      if (gk[k] >= 0) atomic_add(w + (int64_t)gk[k] * ncomp + c0 + c, acc);
+    }
+  }
+  if (part) block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Mass with collocated GLL quadrature: B_L is diagonal (section 5, remark
+// after eq. (mass)); w = Q^T (B~ .* Q u).
+// ---------------------------------------------------------------------------
+template <int P1, typename T>
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Bt,
+    const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0, int ncg, int masked,
+    double *__restrict__ part, const int *__restrict__ done) {
+  using PL = Plane<P1, P1>;
+  constexpr int N3 = P1 * P1 * P1;
+  if (done && *done) return;
+  const int t = threadIdx.x;
+  const bool act = t < PL::USED;
+  const int slot = act ? t / PL::N : 0;
+  const int ij = t % PL::N;
+  const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
+  const bool live = act && e < nelem;
+  int gk[P1];
+  T b[P1];
+#pragma unroll
+  for (int k = 0; k < P1; ++k) {
+    const int v = live ? idx[e * N3 + k * P1 * P1 + ij] : -1;
+    gk[k] = decode_index(v, live, masked);
+    b[k] = live ? Bt[e * N3 + k * P1 * P1 + ij] : T(0);
+  }
+  for (int cc = 0; cc < ncg; ++cc) {
+    double en[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      if (gk[k] < 0) continue;
+      const int64_t o = (int64_t)gk[k] * ncomp + c0 + cc;
+      const T uv = u[o];
+      const T wv = b[k] * uv;
+      en[0] += (double)uv * (double)wv;
+      atomic_add(w + o, wv);
+    }
+    if (part) block_sum_store<1, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0 + cc, 1);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BK1-BK4: Gauss-Legendre quadrature (q > p1). Interpolate to the quadrature
+// points first (u~ = J u), differentiate there with the q x q matrix D~
+// (section 5, eq. (gradr2)-(gradt2)), apply G (stiffness) or B~ (mass), and
+// return with the transposed operations. Thread plane (a, b) over q x q.
+// ---------------------------------------------------------------------------
+template <int P1, int Q, typename T, bool STIFF>
+__global__ __launch_bounds__((Plane<P1, Q>::THREADS)) void k_op_interp(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
+    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp,
+    int c0, int ncg, int masked, double *__restrict__ part, const int *__restrict__ done) {
+  using PL = Plane<P1, Q>;
+  constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QP = Q + 1;
+  static_assert(Q > P1, "interpolating kernel expects q > p1");
+  if (done && *done) return;
+  __shared__ T sJ[Q][P1];
+  __shared__ T sDq[Q][Q];
+  __shared__ T s1[PL::EPB][Q][Q][QP];
+  __shared__ T s2[PL::EPB][Q][Q][QP];
+  __shared__ T s3[PL::EPB][Q][Q][QP];
+  const int t = threadIdx.x;
+  const bool act = t < PL::USED;
+  const int slot = act ? t / PL::N : 0;
+  const int ab = t % PL::N;
+  const int a = ab % Q, b = ab / Q;
+  const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
+  const bool live = act && e < nelem;
+  const bool own = live && a < P1 && b < P1;  // owns node column (i=a, j=b)
+  for (int x = t; x < Q * P1; x += PL::THREADS) sJ[x / P1][x % P1] = basis[x];
+  for (int x = t; x < Q * Q; x += PL::THREADS) sDq[x / Q][x % Q] = basis[2 * Q * P1 + x];
+  int gk[P1];
+#pragma unroll
+  for (int k = 0; k < P1; ++k) {
+    const int v = own ? idx[e * N3 + a + P1 * (b + P1 * k)] : -1;
+    gk[k] = decode_index(v, own, masked);
+  }
+  const T *Ge = Gm + (live ? e : 0) * (STIFF ? 6 : 1) * NQ + ab;
+
+  for (int cc = 0; cc < ncg; ++cc) {
+    const int comp = c0 + cc;
+    T ru[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      ru[k] = gk[k] >= 0 ? u[(int64_t)gk[k] * ncomp + comp] : T(0);
+      if (act && a < P1 && b < P1) s1[slot][k][b][a] = ru[k];
+    }
+    __syncthreads();
+    // interpolate along r: s2[k][j][a] = sum_i J[a][i] u[k][j][i]
+    if (act && b < P1)
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) s += sJ[a][m] * s1[slot][k][b][m];
+        s2[slot][k][b][a] = s;
+      }
+    __syncthreads();
+    // along s: s3[k][b][a] = sum_j J[b][j] s2[k][j][a]
+    if (act)
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) s += sJ[b][m] * s2[slot][k][m][a];
+        s3[slot][k][b][a] = s;
+      }
+    __syncthreads();
+    // along t: uq[c] in registers
+    T uq[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) s += sJ[c][m] * s3[slot][m][b][a];
+      uq[c] = s;
+    }
+    T tv[Q];
+    if constexpr (STIFF) {
+      if (act)
+#pragma unroll
+        for (int c = 0; c < Q; ++c) s1[slot][c][b][a] = uq[c];
+      __syncthreads();
+      T rv[Q];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        T ur = 0, us = 0, ut = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) {
+          ur += sDq[a][m] * s1[slot][c][b][m];
+          us += sDq[b][m] * s1[slot][c][m][a];
+          ut += sDq[c][m] * uq[m];
+        }
+        T g[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) g[n] = live ? Ge[n * NQ + c * Q * Q] : T(0);
+        const T vr = g[0] * ur + g[1] * us + g[2] * ut;
+        const T vs = g[1] * ur + g[3] * us + g[4] * ut;
+        rv[c] = g[2] * ur + g[4] * us + g[5] * ut;
+        if (act) {
+          s2[slot][c][b][a] = vr;
+          s3[slot][c][b][a] = vs;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) {
+          s += sDq[m][c] * rv[m];
+          s += sDq[m][a] * s2[slot][c][b][m];
+          s += sDq[m][b] * s3[slot][c][m][a];
+        }
+        tv[c] = s;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < Q; ++c) tv[c] = (live ? Ge[c * Q * Q] : T(0)) * uq[c];
+    }
+    __syncthreads();
+    // transposed interpolation along t: s1[k][b][a] = sum_c J[c][k] tv[c]
+    if (act)
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) s += sJ[c][k] * tv[c];
+        s1[slot][k][b][a] = s;
+      }
+    __syncthreads();
+    // along s: s2[k][j][a] = sum_b J[b][j] s1[k][b][a]
+    if (act && b < P1)
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) s += sJ[m][b] * s1[slot][k][m][a];
+        s2[slot][k][b][a] = s;
+      }
+    __syncthreads();
+    // along r, energy, scatter
+    double en[1] = {0.0};
+    if (act && a < P1 && b < P1)
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) s += sJ[m][a] * s2[slot][k][b][m];
+        en[0] += (double)ru[k] * (double)s;
+        if (gk[k] >= 0) atomic_add(w + (int64_t)gk[k] * ncomp + comp, s);
+      }
+    if (part) block_sum_store<1, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + comp, 1);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal of the assembled operator (Jacobi preconditioner, section 3).
+// diag(A^e)_{ijk} = sum_{mm'} sum_{abc} G_mm'(a,b,c) phi_m phi_m' with
+// phi_1 = D[a][i] J[b][j] J[c][k], phi_2 = J[a][i] D[b][j] J[c][k],
+// phi_3 = J[a][i] J[b][j] D[c][k]; mass: sum B~ J[a][i]^2 J[b][j]^2 J[c][k]^2.
+// Sum-factorised per element (contract a, then b, then c), scatter-added.
+// Runtime sizes; dynamic LDS of q^3 + q^2 p1 + q p1^2 + p1^3 + 2 q p1 values.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_diag(int64_t nelem, int p1, int q, int stiff,
+                                              const int32_t *__restrict__ idx,
+                                              const double *__restrict__ Gm,
+                                              const double *__restrict__ basis,
+                                              double *__restrict__ d, int masked) {
+  extern __shared__ double dsm[];
+  const int q3 = q * q * q, n3 = p1 * p1 * p1;
+  double *sg = dsm;                // [c][b][a]      q^3
+  double *t1 = sg + q3;            // [c][b][i]      q^2 p1
+  double *t2 = t1 + q * q * p1;    // [c][j][i]      q p1^2
+  double *sd = t2 + q * p1 * p1;   // [k][j][i]      p1^3
+  double *sJ = sd + n3;            // q x p1
+  double *sD = sJ + q * p1;        // q x p1
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int x = t; x < q * p1; x += nt) {
+    sJ[x] = basis[x];
+    sD[x] = basis[q * p1 + x];
+  }
+  for (int x = t; x < n3; x += nt) sd[x] = 0.0;
+  const int nterms = stiff ? 6 : 1;
+  const int pm[6] = {0, 0, 0, 1, 1, 2}, pn[6] = {0, 1, 2, 1, 2, 2};
+  __syncthreads();
+  for (int term = 0; term < nterms; ++term) {
+    const double *src = stiff ? Gm + (e * 6 + term) * q3 : Gm + e * q3;
+    for (int x = t; x < q3; x += nt) sg[x] = src[x];
+    const int m0 = stiff ? pm[term] : -1, m1 = stiff ? pn[term] : -1;
+    const double fac = (stiff && m0 != m1) ? 2.0 : 1.0;
+    __syncthreads();
+    // direction dir uses F(m0,dir) * F(m1,dir), F = D if m == dir else J
+    for (int x = t; x < q * q * p1; x += nt) {
+      const int i = x % p1, bb = (x / p1) % q, c = x / (p1 * q);
+      double s = 0.0;
+      for (int a = 0; a < q; ++a) {
+        const double f0 = (m0 == 0 ? sD : sJ)[a * p1 + i];
+        const double f1 = (m1 == 0 ? sD : sJ)[a * p1 + i];
+        s += f0 * f1 * sg[(c * q + bb) * q + a];
+      }
+      t1[x] = s;
+    }
+    __syncthreads();
+    for (int x = t; x < q * p1 * p1; x += nt) {
+      const int i = x % p1, j = (x / p1) % p1, c = x / (p1 * p1);
+      double s = 0.0;
+      for (int bb = 0; bb < q; ++bb) {
+        const double f0 = (m0 == 1 ? sD : sJ)[bb * p1 + j];
+        const double f1 = (m1 == 1 ? sD : sJ)[bb * p1 + j];
+        s += f0 * f1 * t1[(c * q + bb) * p1 + i];
+      }
+      t2[x] = s;
+    }
+    __syncthreads();
+    for (int x = t; x < n3; x += nt) {
+      const int i = x % p1, j = (x / p1) % p1, k = x / (p1 * p1);
+      double s = 0.0;
+      for (int c = 0; c < q; ++c) {
+        const double f0 = (m0 == 2 ? sD : sJ)[c * p1 + k];
+        const double f1 = (m1 == 2 ? sD : sJ)[c * p1 + k];
+        s += f0 * f1 * t2[(c * p1 + j) * p1 + i];
+      }
+      sd[x] += fac * s;
+    }
+    __syncthreads();
+  }
+  for (int x = t; x < n3; x += nt) {
+    const int v = idx[e * n3 + x];
+    const int g = decode_index(v, true, masked);
+    if (g >= 0) atomic_add(d + g, sd[x]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient with respect to the coefficient at the quadrature points
+// (collocated GLL): g_q = - sum_c (D lam_c)_q^T G_q (D u_c)_q.
+// ---------------------------------------------------------------------------
+template <int P1>
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
+    int64_t nelem, const int32_t *__restrict__ idx, const double *__restrict__ G,
+    const double *__restrict__ basis, const double *__restrict__ lam,
+    const double *__restrict__ u, double *__restrict__ gout, int ncomp) {
+  using PL = Plane<P1, P1>;
+  constexpr int N3 = P1 * P1 * P1, PAD = P1 + 1;
+  __shared__ double sD[P1][P1];
+  __shared__ double sl[PL::EPB][P1][P1][PAD];
+  __shared__ double su[PL::EPB][P1][P1][PAD];
+  const int t = threadIdx.x;
+  const bool act = t < PL::USED;
+  const int slot = act ? t / PL::N : 0;
+  const int ij = t % PL::N;
+  const int i = ij % P1, j = ij / P1;
+  const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
+  const bool live = act && e < nelem;
+  for (int x = t; x < P1 * P1; x += PL::THREADS) sD[x / P1][x % P1] = basis[P1 * P1 + x];
+  int gk[P1];
+#pragma unroll
+  for (int k = 0; k < P1; ++k) {
+    const int v = live ? idx[e * N3 + i + P1 * (j + P1 * k)] : -1;
+    gk[k] = decode_index(v, live, 1);
+  }
+  double acc[P1];
+#pragma unroll
+  for (int k = 0; k < P1; ++k) acc[k] = 0.0;
+  for (int c = 0; c < ncomp; ++c) {
+    double rl[P1], rv[P1];
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      rl[k] = gk[k] >= 0 ? lam[(int64_t)gk[k] * ncomp + c] : 0.0;
+      rv[k] = gk[k] >= 0 ? u[(int64_t)gk[k] * ncomp + c] : 0.0;
+      if (act) {
+        sl[slot][k][j][i] = rl[k];
+        su[slot][k][j][i] = rv[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      double lr = 0, ls = 0, lt = 0, ur = 0, us = 0, ut = 0;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) {
+        lr += sD[i][m] * sl[slot][k][j][m];
+        ls += sD[j][m] * sl[slot][k][m][i];
+        lt += sD[k][m] * rl[m];
+        ur += sD[i][m] * su[slot][k][j][m];
+        us += sD[j][m] * su[slot][k][m][i];
+        ut += sD[k][m] * rv[m];
+      }
+      const double *Gq = G + (live ? e : 0) * 6 * N3 + k * P1 * P1 + ij;
+      double g[6];
+#pragma unroll
+      for (int n = 0; n < 6; ++n) g[n] = live ? Gq[n * N3] : 0.0;
+      acc[k] += lr * (g[0] * ur + g[1] * us + g[2] * ut) + ls * (g[1] * ur + g[3] * us + g[4] * ut) +
+                lt * (g[2] * ur + g[4] * us + g[5] * ut);
+    }
+    __syncthreads();
+  }
+  if (live)
+#pragma unroll
+    for (int k = 0; k < P1; ++k) gout[e * N3 + k * P1 * P1 + ij] = -acc[k];
+}
+
+}  // namespace bp

@@ -1,0 +1,47 @@
+// Host-callable launchers of the device kernels.
+#pragma once
+
+#include "bp_internal.h"
+
+namespace bp {
+
+// operator kernels (ops.hip)
+bool kernels_cover(int p, int q, int quad);
+int64_t plane_epb(int p1, int q);
+int64_t apply_blocks(const bp_op_s *op);
+int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
+                 double *part, const int *done, hipStream_t s);
+int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_t s);
+int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, double *g,
+                      hipStream_t s);
+
+// vector kernels (vec.hip); sizes are global nodes n and components nc
+constexpr int kVecThreads = 256;
+constexpr int64_t kVecMaxBlocks = 2048;
+int64_t vec_blocks(int64_t n);
+void fill_f64(double *x, int64_t n, double v, hipStream_t s);
+void fill_f32(float *x, int64_t n, float v, hipStream_t s);
+void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,
+                    int64_t nelem, int nq, hipStream_t s);
+void to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStream_t s);
+
+// CG steps; part holds per-block partial sums, sc the device scalars.
+template <typename T>
+void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, double *part,
+             DevScalars *sc, hipStream_t s);
+void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s);
+template <typename T>
+void cg_update_xr(int nc, int64_t n, T *x, const T *p, T *r, T *w, const T *dinv, double *part,
+                  DevScalars *sc, hipStream_t s);
+void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s);
+template <typename T>
+void cg_update_p(int nc, int64_t n, T *p, const T *r, const T *dinv, DevScalars *sc,
+                 hipStream_t s);
+
+// defect correction helpers (FP64 outer loop)
+void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,
+                 DevScalars *sc, hipStream_t s);
+void dc_accumulate(int64_t n, double *x, const float *d, hipStream_t s);
+
+}  // namespace bp

@@ -1,0 +1,152 @@
+// Launchers of the operator kernels: dispatch on (p1, q, quadrature,
+// components, precision) to the compiled template instances.
+#include "bp_internal.h"
+#include "kernels.hpp"
+#include "launch.h"
+
+namespace bp {
+
+int64_t plane_epb(int p1, int q) {
+  const int m = p1 > q ? p1 : q;
+  const int n = m * m;
+  return n >= 64 ? 1 : 64 / n;
+}
+
+int64_t apply_blocks(const bp_op_s *op) {
+  const int64_t epb = plane_epb(op->p1, op->q);
+  return (op->nelem + epb - 1) / epb;
+}
+
+namespace {
+
+template <int P1, typename T>
+int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *u, T *w, int masked,
+                 double *part, const int *done, hipStream_t s) {
+  using PL = Plane<P1, P1>;
+  const int64_t nb = apply_blocks(op);
+  for (int c0 = 0; c0 < op->ncomp;) {
+    const int g = op->ncomp - c0 >= 3 ? 3 : op->ncomp - c0;
+    if (g == 3)
+      hipLaunchKernelGGL((k_stiff_colloc<P1, 3, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
+                         op->idx, G, basis, u, w, op->ncomp, c0, masked, part, done);
+    else if (g == 2)
+      hipLaunchKernelGGL((k_stiff_colloc<P1, 2, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
+                         op->idx, G, basis, u, w, op->ncomp, c0, masked, part, done);
+    else
+      hipLaunchKernelGGL((k_stiff_colloc<P1, 1, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
+                         op->idx, G, basis, u, w, op->ncomp, c0, masked, part, done);
+    c0 += g;
+  }
+  return BP_OK;
+}
+
+template <int P1, typename T>
+int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, double *part,
+                const int *done, hipStream_t s) {
+  using PL = Plane<P1, P1>;
+  hipLaunchKernelGGL((k_mass_colloc<P1, T>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
+                     op->nelem, op->idx, Bt, u, w, op->ncomp, 0, op->ncomp, masked, part, done);
+  return BP_OK;
+}
+
+template <int P1, int Q, typename T, bool STIFF>
+int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int masked,
+           double *part, const int *done, hipStream_t s) {
+  using PL = Plane<P1, Q>;
+  hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(apply_blocks(op)), dim3(PL::THREADS),
+                     0, s, op->nelem, op->idx, Gm, basis, u, w, op->ncomp, 0, op->ncomp, masked,
+                     part, done);
+  return BP_OK;
+}
+
+template <typename T>
+int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *basis, const T *u,
+             T *w, int masked, double *part, const int *done, hipStream_t s) {
+  const bool stiff = which == BP_STIFF;
+  if (op->colloc) {
+#define BP_CASE(P)                                                                  \
+  case P:                                                                           \
+    return stiff ? stiff_colloc<P, T>(op, G, basis, u, w, masked, part, done, s)    \
+                 : mass_colloc<P, T>(op, Bt, u, w, masked, part, done, s);
+    switch (op->p1) {
+      BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
+    }
+#undef BP_CASE
+  } else if (op->q == op->p1 + 1) {
+#define BP_CASE(P)                                                                   \
+  case P:                                                                            \
+    return stiff ? interp<P, P + 1, T, true>(op, G, basis, u, w, masked, part, done, s) \
+                 : interp<P, P + 1, T, false>(op, Bt, basis, u, w, masked, part, done, s);
+    switch (op->p1) {
+      BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
+    }
+#undef BP_CASE
+  }
+  return set_error(BP_ERR_ARG, "no compiled kernel for this (p, q, quadrature)");
+}
+
+template <int P1>
+void grad_colloc(const bp_op_s *op, const double *lam, const double *u, double *g,
+                 hipStream_t s) {
+  using PL = Plane<P1, P1>;
+  hipLaunchKernelGGL((k_grad_kappa_colloc<P1>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
+                     op->nelem, op->idx, op->G, op->basis_d, lam, u, g, op->ncomp);
+}
+
+}  // namespace
+
+bool kernels_cover(int p, int q, int quad) {
+  if (p < 1 || p > 8) return false;
+  if (quad == BP_QUAD_GLL) return q == p + 1;
+  return q == p + 2;
+}
+
+int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
+                 double *part, const int *done, hipStream_t s) {
+  int rc;
+  if (f32) {
+    const float *G = op->kappa_set ? op->Gk32 : op->G32;
+    rc = dispatch<float>(op, which, G, op->Bt32, op->basis32, (const float *)u, (float *)w,
+                         masked, part, done, s);
+  } else {
+    const double *G = op->kappa_set ? op->Gk : op->G;
+    rc = dispatch<double>(op, which, G, op->Bt, op->basis_d, (const double *)u, (double *)w,
+                          masked, part, done, s);
+  }
+  if (rc != BP_OK) return rc;
+  BP_HIP(hipGetLastError());
+  return BP_OK;
+}
+
+int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_t s) {
+  const int p1 = op->p1, q = op->q;
+  const size_t lds = sizeof(double) *
+                     ((size_t)q * q * q + (size_t)q * q * p1 + (size_t)q * p1 * p1 +
+                      (size_t)p1 * p1 * p1 + 2 * (size_t)q * p1);
+  const bool stiff = which == BP_STIFF;
+  const double *Gm = stiff ? (op->kappa_set ? op->Gk : op->G) : op->Bt;
+  hipLaunchKernelGGL(k_diag, dim3(op->nelem), dim3(256), lds, s, op->nelem, p1, q, stiff ? 1 : 0,
+                     op->idx, Gm, op->basis_d, d, masked ? 1 : 0);
+  BP_HIP(hipGetLastError());
+  return BP_OK;
+}
+
+int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, double *g,
+                      hipStream_t s) {
+  if (!op->colloc) return set_error(BP_ERR_ARG, "bp_grad_kappa: only collocated GLL operators");
+  switch (op->p1) {
+    case 2: grad_colloc<2>(op, lam, u, g, s); break;
+    case 3: grad_colloc<3>(op, lam, u, g, s); break;
+    case 4: grad_colloc<4>(op, lam, u, g, s); break;
+    case 5: grad_colloc<5>(op, lam, u, g, s); break;
+    case 6: grad_colloc<6>(op, lam, u, g, s); break;
+    case 7: grad_colloc<7>(op, lam, u, g, s); break;
+    case 8: grad_colloc<8>(op, lam, u, g, s); break;
+    case 9: grad_colloc<9>(op, lam, u, g, s); break;
+    default: return set_error(BP_ERR_ARG, "bp_grad_kappa: order not compiled");
+  }
+  BP_HIP(hipGetLastError());
+  return BP_OK;
+}
+
+}  // namespace bp

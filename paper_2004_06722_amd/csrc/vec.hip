@@ -1,0 +1,402 @@
+// Streaming vector kernels of the Jacobi-PCG iteration (section 3; the
+// vector operations are the "n or 2n flops, one or two words per operation"
+// updates of section 8) with deterministic reductions: every work-group
+// writes its partial sums, and a single work-group adds the partials in a
+// fixed order and updates alpha, beta and the convergence flag on the
+// device, so the host never waits inside the iteration.
+#include <cmath>
+
+#include "bp_internal.h"
+#include "launch.h"
+
+namespace bp {
+
+namespace {
+
+constexpr int kFinThreads = 1024;
+
+// Block sum of NC doubles per thread into part[blk * width + off + c].
+template <int NC>
+__device__ __forceinline__ void block_partials(double (&v)[NC], double *part, int width, int off) {
+  constexpr int NW = kVecThreads / 64;
+  __shared__ double red[NW][NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    v[c] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[wid][c] = v[c];
+  __syncthreads();
+  if (threadIdx.x < NC) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[k][threadIdx.x];
+    part[(int64_t)blockIdx.x * width + off + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Fixed-order sum of `width` columns over nb rows: res[col] (shared).
+__device__ void reduce_columns(const double *__restrict__ part, int64_t nb, int width,
+                               double *res) {
+  __shared__ double sh[kFinThreads];
+  for (int col = 0; col < width; ++col) {
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < nb; r += kFinThreads) s += part[r * width + col];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kFinThreads / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) res[col] = sh[0];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool converged(const DevScalars *sc, int nc) {
+  bool ok = true;
+  for (int c = 0; c < nc; ++c) {
+    const double bb = sc->bb[c] > 0.0 ? sc->bb[c] : 1.0;
+    ok = ok && (sc->rr[c] <= sc->tol2 * bb);
+  }
+  return ok;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kVecThreads)
+    x[i] = v;
+}
+
+// r = b - w (w holds A x0), w = 0, p = z = dinv r; partials r.z, r.r, b.b.
+// Entries of b on Dirichlet nodes are treated as zero.
+template <int NC, typename T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_init(int64_t n, const T *__restrict__ b,
+                                                         T *__restrict__ r, T *__restrict__ w,
+                                                         T *__restrict__ p,
+                                                         const T *__restrict__ dinv,
+                                                         double *__restrict__ part) {
+  double rz[NC], rr[NC], bb[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) rz[c] = rr[c] = bb[c] = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kVecThreads) {
+    const T di = dinv[v];
+    // dinv = 0 exactly on Dirichlet nodes: b is read as 0 there
+    const bool free = di != T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t o = v * NC + c;
+      const T bv = free ? b[o] : T(0);
+      const T rv = free ? bv - w[o] : T(0);
+      const T z = di * rv;
+      r[o] = rv;
+      p[o] = z;
+      w[o] = T(0);
+      rz[c] += (double)rv * (double)z;
+      rr[c] += (double)rv * (double)rv;
+      bb[c] += (double)bv * (double)bv;
+    }
+  }
+  block_partials<NC>(rz, part, 3 * NC, 0);
+  block_partials<NC>(rr, part, 3 * NC, NC);
+  block_partials<NC>(bb, part, 3 * NC, 2 * NC);
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restrict__ part,
+                                                          int64_t nb, int nc, DevScalars *sc) {
+  __shared__ double res[3 * kMaxComp];
+  reduce_columns(part, nb, 3 * nc, res);
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int c = 0; c < nc; ++c) {
+      sc->rz[c] = res[c];
+      sc->rr[c] = res[nc + c];
+      sc->bb[c] = res[2 * nc + c];
+      sc->alpha[c] = sc->beta[c] = 0.0;
+      bad |= !isfinite(res[c]) || !isfinite(res[nc + c]) || !isfinite(res[2 * nc + c]);
+    }
+    sc->iters = 0;
+    sc->breakdown = 0;
+    sc->nonfinite = bad;
+    sc->done = bad || (!sc->fixed && converged(sc, nc));
+  }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restrict__ part,
+                                                           int64_t nb, int nc, DevScalars *sc) {
+  if (sc->done) return;
+  __shared__ double res[kMaxComp];
+  reduce_columns(part, nb, nc, res);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nc; ++c) {
+      const double pap = res[c];
+      sc->pap[c] = pap;
+      sc->alpha[c] = pap != 0.0 ? sc->rz[c] / pap : 0.0;
+      if (pap < 0.0) sc->breakdown = 1;
+      if (!isfinite(pap)) sc->nonfinite = 1;
+    }
+}
+
+// x += alpha p; r -= alpha w; w = 0; partials r.z (z = dinv r) and r.r.
+template <int NC, typename T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_xr(
+    int64_t n, T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r, T *__restrict__ w,
+    const T *__restrict__ dinv, double *__restrict__ part, const DevScalars *__restrict__ sc) {
+  if (sc->done) return;
+  T al[NC];
+  double rz[NC], rr[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    al[c] = (T)sc->alpha[c];
+    rz[c] = rr[c] = 0.0;
+  }
+  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kVecThreads) {
+    const T di = dinv[v];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t o = v * NC + c;
+      x[o] += al[c] * p[o];
+      const T rv = r[o] - al[c] * w[o];
+      r[o] = rv;
+      w[o] = T(0);
+      rz[c] += (double)rv * (double)(di * rv);
+      rr[c] += (double)rv * (double)rv;
+    }
+  }
+  block_partials<NC>(rz, part, 2 * NC, 0);
+  block_partials<NC>(rr, part, 2 * NC, NC);
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restrict__ part,
+                                                          int64_t nb, int nc, DevScalars *sc) {
+  if (sc->done) return;
+  __shared__ double res[2 * kMaxComp];
+  reduce_columns(part, nb, 2 * nc, res);
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < nc; ++c) {
+      const double rz = res[c];
+      sc->beta[c] = sc->rz[c] != 0.0 ? rz / sc->rz[c] : 0.0;
+      sc->rz[c] = rz;
+      sc->rr[c] = res[nc + c];
+      if (!isfinite(rz) || !isfinite(res[nc + c])) sc->nonfinite = 1;
+    }
+    sc->iters += 1;
+    if (sc->nonfinite || (!sc->fixed && converged(sc, nc))) sc->done = 1;
+  }
+}
+
+// p = dinv r + beta p
+template <int NC, typename T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_p(int64_t n, T *__restrict__ p,
+                                                             const T *__restrict__ r,
+                                                             const T *__restrict__ dinv,
+                                                             const DevScalars *__restrict__ sc) {
+  if (sc->done) return;
+  T be[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) be[c] = (T)sc->beta[c];
+  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kVecThreads) {
+    const T di = dinv[v];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t o = v * NC + c;
+      p[o] = di * r[o] + be[c] * p[o];
+    }
+  }
+}
+
+// r = b - w, w = 0; partials r.r and b.b
+template <int NC>
+__global__ __launch_bounds__(kVecThreads) void k_dc_residual(int64_t n, const double *__restrict__ b,
+                                                             double *__restrict__ r,
+                                                             double *__restrict__ w,
+                                                             double *__restrict__ part) {
+  double rr[NC], bb[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) rr[c] = bb[c] = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kVecThreads) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t o = v * NC + c;
+      const double rv = b[o] - w[o];
+      r[o] = rv;
+      w[o] = 0.0;
+      rr[c] += rv * rv;
+      bb[c] += b[o] * b[o];
+    }
+  }
+  block_partials<NC>(rr, part, 2 * NC, 0);
+  block_partials<NC>(bb, part, 2 * NC, NC);
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_norms(const double *__restrict__ part,
+                                                           int64_t nb, int nc, DevScalars *sc) {
+  __shared__ double res[2 * kMaxComp];
+  reduce_columns(part, nb, 2 * nc, res);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nc; ++c) {
+      sc->rr[c] = res[c];
+      sc->bb[c] = res[nc + c];
+    }
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_to_f32(const double *__restrict__ s,
+                                                        float *__restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kVecThreads)
+    d[i] = (float)s[i];
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_accumulate(double *__restrict__ x,
+                                                            const float *__restrict__ d,
+                                                            int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kVecThreads)
+    x[i] += (double)d[i];
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_invert(const double *__restrict__ d,
+                                                        double *__restrict__ di,
+                                                        float *__restrict__ di32, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kVecThreads) {
+    const double v = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
+    di[i] = v;
+    if (di32) di32[i] = (float)v;
+  }
+}
+
+// Gk[e][m][q] = kappa[e][q] * G[e][m][q]
+__global__ __launch_bounds__(kVecThreads) void k_scale_geometry(const double *__restrict__ G,
+                                                                const double *__restrict__ kap,
+                                                                double *__restrict__ Gk,
+                                                                float *__restrict__ Gk32,
+                                                                int64_t nelem, int nq) {
+  const int64_t total = nelem * 6 * nq;
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * kVecThreads) {
+    const int64_t e = i / (6 * (int64_t)nq);
+    const int64_t qp = i % nq;
+    const double v = kap[e * nq + qp] * G[i];
+    Gk[i] = v;
+    if (Gk32) Gk32[i] = (float)v;
+  }
+}
+
+}  // namespace
+
+int64_t vec_blocks(int64_t n) {
+  int64_t b = (n + kVecThreads - 1) / kVecThreads;
+  if (b > kVecMaxBlocks) b = kVecMaxBlocks;
+  return b < 1 ? 1 : b;
+}
+
+void fill_f64(double *x, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<double>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, x, n, v);
+}
+void fill_f32(float *x, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<float>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, x, n, v);
+}
+void to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, src, dst, n);
+}
+void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_invert, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, d, dinv, dinv32, n);
+}
+void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,
+                    int64_t nelem, int nq, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_geometry, dim3(vec_blocks(nelem * 6 * nq)), dim3(kVecThreads), 0, s,
+                     G, kappa, Gk, Gk32, nelem, nq);
+}
+
+#define BP_NC_SWITCH(nc, MACRO) \
+  switch (nc) {                 \
+    case 1: MACRO(1); break;    \
+    case 2: MACRO(2); break;    \
+    case 3: MACRO(3); break;    \
+    case 4: MACRO(4); break;    \
+    case 5: MACRO(5); break;    \
+    case 6: MACRO(6); break;    \
+    case 7: MACRO(7); break;    \
+    default: MACRO(8); break;   \
+  }
+
+template <typename T>
+void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, double *part,
+             DevScalars *sc, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+#define L(NC) \
+  hipLaunchKernelGGL((k_cg_init<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, b, r, w, p, dinv, part)
+  BP_NC_SWITCH(nc, L)
+#undef L
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+}
+
+void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+}
+
+template <typename T>
+void cg_update_xr(int nc, int64_t n, T *x, const T *p, T *r, T *w, const T *dinv, double *part,
+                  DevScalars *sc, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+#define L(NC)                                                                                  \
+  hipLaunchKernelGGL((k_cg_update_xr<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, x, p, r, w, \
+                     dinv, part, sc)
+  BP_NC_SWITCH(nc, L)
+#undef L
+}
+
+void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+}
+
+template <typename T>
+void cg_update_p(int nc, int64_t n, T *p, const T *r, const T *dinv, DevScalars *sc,
+                 hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+#define L(NC) \
+  hipLaunchKernelGGL((k_cg_update_p<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, p, r, dinv, sc)
+  BP_NC_SWITCH(nc, L)
+#undef L
+}
+
+void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,
+                 DevScalars *sc, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+#define L(NC) \
+  hipLaunchKernelGGL((k_dc_residual<NC>), dim3(nb), dim3(kVecThreads), 0, s, n, b, r, w, part)
+  BP_NC_SWITCH(nc, L)
+#undef L
+  hipLaunchKernelGGL(k_fin_norms, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+}
+
+void dc_accumulate(int64_t n, double *x, const float *d, hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, x, d, n);
+}
+
+template void cg_init<double>(int, int64_t, const double *, double *, double *, double *,
+                              const double *, double *, DevScalars *, hipStream_t);
+template void cg_init<float>(int, int64_t, const float *, float *, float *, float *,
+                             const float *, double *, DevScalars *, hipStream_t);
+template void cg_update_xr<double>(int, int64_t, double *, const double *, double *, double *,
+                                   const double *, double *, DevScalars *, hipStream_t);
+template void cg_update_xr<float>(int, int64_t, float *, const float *, float *, float *,
+                                  const float *, double *, DevScalars *, hipStream_t);
+template void cg_update_p<double>(int, int64_t, double *, const double *, const double *,
+                                  DevScalars *, hipStream_t);
+template void cg_update_p<float>(int, int64_t, float *, const float *, const float *,
+                                 DevScalars *, hipStream_t);
+
+}  // namespace bp

@@ -1,0 +1,79 @@
+"""Algorithmic byte and flop counts of the bake-off hot path.
+
+Bytes are what the method itself must move per CG iteration: the stored
+geometric factors (section 5 after eq. (gij): 6 q^3 words per element for the
+stiffness, q^3 for B~ of eq. (mass)), the int32 gather map (p1^3 per element;
+the global tensor layout may not be exploited, section 3), and the vectors.
+Vector words per DOF and iteration: the operator reads p and writes w (2),
+the CG update reads x, p, r, w, dinv and writes x, r (7), the direction
+update reads r, dinv, p and writes p (4): 13 in all. DOFs are n = p^3 E
+(section 2) per component.
+
+Flops follow section 5: eq. (work2)/(work3) for the sum-factorised
+stiffness, 4 p1^4 (g^3 + g^2 + g) for the mass, with J^ = I for collocated
+GLL (the derivative contractions alone: 12 p1^4 + 15 p1^3).
+"""
+from __future__ import annotations
+
+VECTOR_WORDS_OPERATOR = 2
+VECTOR_WORDS_CG = 11
+
+
+def quadrature(bp: int, p: int) -> int:
+    return p + 1 if bp in (5, 6) else p + 2
+
+
+def geometry_words(bp: int, p: int) -> int:
+    q = quadrature(bp, p)
+    return (6 if bp >= 3 else 1) * q ** 3
+
+
+def apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
+    """Bytes of one operator application (geometry + map + u in + w out)."""
+    n = p ** 3 * E
+    return E * (word * geometry_words(bp, p) + 4 * (p + 1) ** 3) \
+        + word * VECTOR_WORDS_OPERATOR * n * ncomp
+
+
+def iteration_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
+    """Bytes of one CG iteration (operator + vector updates)."""
+    n = p ** 3 * E
+    return apply_bytes(bp, p, E, ncomp, word) + word * VECTOR_WORDS_CG * n * ncomp
+
+
+def work_direct(p1: int, gamma: float) -> float:
+    """Eq. (work2): D_j applied in factored form, (J^ x J^ x D^) per direction."""
+    return 4 * p1 ** 4 * (3 * gamma ** 3 + 3 * gamma ** 2 + 2 * gamma) + 15 * gamma ** 3 * p1 ** 3
+
+
+def work_interpolate_first(p1: int, gamma: float) -> float:
+    """Eq. (work3): interpolate to the quadrature points, differentiate there."""
+    return 4 * p1 ** 4 * (3 * gamma ** 4 + gamma ** 3 + gamma ** 2 + gamma) \
+        + 15 * gamma ** 3 * p1 ** 3
+
+
+def work_mass(p1: int, gamma: float) -> float:
+    """Section 5 after eq. (mass): 4 p1^4 (g^3 + g^2 + g) (+ q^3 for B~)."""
+    return 4 * p1 ** 4 * (gamma ** 3 + gamma ** 2 + gamma) + (gamma * p1) ** 3
+
+
+def apply_flops_per_element(bp: int, p: int) -> float:
+    p1 = p + 1
+    q = quadrature(bp, p)
+    g = q / p1
+    if bp in (5, 6):
+        return 12 * p1 ** 4 + 15 * p1 ** 3      # J^ = I: only the D^ contractions
+    if bp in (3, 4):
+        return work_interpolate_first(p1, g)
+    return work_mass(p1, g)
+
+
+def iteration_flops(bp: int, p: int, E: int, ncomp: int = 1) -> float:
+    """Operator flops + 12 flops per DOF for the CG vector updates and dots."""
+    n = p ** 3 * E
+    return (apply_flops_per_element(bp, p) * E + 12 * n) * ncomp
+
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, published
+FP32_PEAK_TFLOPS = 157.3

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Sizes span several work-groups with a ragged last one; the bar is the
+normwise relative FP64 tolerance 1e-12 (apply, diagonal, CG iterates,
+gradient) unless a test states otherwise with its reason.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import adjoint, mixed
+from oracle.assembled import assemble
+from oracle.operators import MASS, STIFF
+from oracle.pcg import pcg
+from tests.gpu_cases import TOL, Case, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def grid_for(p):
+    # E = 27 (ragged against 16, 7 and 4 elements per work-group) or 12
+    return (3, 3, 3) if p <= 4 else (3, 2, 2)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("bp", [1, 3, 5])
+def test_apply_matches_oracle(bp, p):
+    c = Case(bp, p, *grid_for(p), seed=p)
+    try:
+        u = c.vec(10 + p)
+        for which in (MASS, STIFF):
+            for masked in (False, True):
+                w = host(c.op.apply(which, dev(u), masked=masked))
+                ref = c.disc.apply(which, u, masked=masked)
+                assert rel(w, ref) <= TOL, (which, masked, rel(w, ref))
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("bp,p,ncomp", [(2, 3, 3), (4, 4, 3), (6, 7, 3), (6, 5, 8), (5, 2, 2)])
+def test_vector_components_match_oracle(bp, p, ncomp):
+    c = Case(bp, p, *grid_for(p), seed=3, ncomp=ncomp)
+    try:
+        u = c.vec(20)
+        which = MASS if bp <= 2 else STIFF
+        w = host(c.op.apply(which, dev(u), masked=True))
+        ref = c.disc.apply(which, u, masked=True)
+        for k in range(ncomp):
+            assert rel(w[:, k], ref[:, k]) <= TOL
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("bp,p", [(1, 2), (1, 7), (3, 1), (3, 5), (3, 8), (5, 1), (5, 4), (5, 7), (5, 8)])
+def test_diagonal_matches_oracle(bp, p):
+    c = Case(bp, p, *grid_for(p), seed=4)
+    try:
+        for which in (MASS, STIFF):
+            for masked in (False, True):
+                d = host(c.op.diag(which, masked=masked))
+                assert rel(d, c.disc.diag(which, masked=masked)) <= TOL
+    finally:
+        c.close()
+
+
+def test_diagonal_equals_assembled_diagonal():
+    c = Case(3, 3, 2, 2, 2, seed=5)
+    try:
+        A = assemble(c.disc, STIFF, masked=True)
+        assert rel(host(c.op.diag(STIFF)), A.diagonal()) <= TOL
+    finally:
+        c.close()
+
+
+def test_fp32_apply_matches_single_precision_oracle():
+    c = Case(5, 7, 3, 2, 2, seed=6, fp32=True)
+    try:
+        u = c.vec(7) * (1 - c.mesh.boundary)
+        w32 = host(c.op.apply(STIFF, dev(u.astype(np.float32))))
+        ref32 = mixed.apply_stiff_f32(c.disc, u.astype(np.float32))
+        ref64 = c.disc.apply(STIFF, u)
+        # float32 rounding of G, D and the sums: a few ulp times the
+        # contraction length, relative to the result's norm
+        assert rel(w32, ref64) < 2e-6
+        assert rel(w32, ref32) < 2e-6
+    finally:
+        c.close()
+
+
+def manufactured_rhs(c):
+    f = synth.manufactured_f(c.mesh.global_coords())
+    return c.disc.apply(MASS, f, masked=False) * c.disc.mask
+
+
+def test_pcg_iterates_match_oracle_config1():
+    c = Case(5, 3, 4, 4, 4, seed=0)
+    try:
+        b = manufactured_rhs(c)
+        rec = []
+        pcg(lambda v: c.disc.apply(STIFF, v), b, c.disc.jacobi_inverse(STIFF), maxit=10,
+            fixed_iters=True, record=rec)
+        bd = dev(b)
+        for k in (1, 2, 3, 5, 10):
+            x, st = c.op.pcg_solve(bd, maxit=k, fixed_iters=True)
+            assert st["iters"] == k
+            assert rel(host(x), rec[k - 1]) <= TOL, (k, rel(host(x), rec[k - 1]))
+    finally:
+        c.close()
+
+
+def test_pcg_converged_solution_config1():
+    import scipy.sparse.linalg as spla
+    c = Case(5, 3, 4, 4, 4, seed=0)
+    try:
+        b = manufactured_rhs(c)
+        x, st = c.op.pcg_solve(dev(b), rtol=1e-14, maxit=5000)
+        assert st["converged"] and st["rel_res"][0] <= 1e-14
+        xo, info = pcg(lambda v: c.disc.apply(STIFF, v), b, c.disc.jacobi_inverse(STIFF),
+                       rtol=1e-14, maxit=5000)
+        inner = c.mesh.boundary == 0
+        A = assemble(c.disc, STIFF).tocsr()[inner][:, inner]
+        xd = np.zeros_like(b)
+        xd[inner] = spla.spsolve(A.tocsc(), b[inner])
+        xg = host(x)
+        assert rel(xg, xd) <= TOL
+        assert rel(xg, xo) <= TOL
+        # tolerance mode: same stopping iteration as the oracle, +-1
+        x8, st8 = c.op.pcg_solve(dev(b), rtol=1e-8, maxit=5000)
+        _, info8 = pcg(lambda v: c.disc.apply(STIFF, v), b, c.disc.jacobi_inverse(STIFF),
+                       rtol=1e-8, maxit=5000)
+        assert abs(st8["iters"] - info8["iters"]) <= 1
+        assert st8["rel_res"][0] <= 1e-8
+    finally:
+        c.close()
+
+
+def test_mass_solve_bp1_matches_oracle():
+    c = Case(1, 3, 3, 3, 2, seed=8)
+    try:
+        b = c.vec(0)
+        x, st = c.op.pcg_solve(dev(b), which=MASS, rtol=1e-14, maxit=2000)
+        xo, _ = pcg(lambda v: c.disc.apply(MASS, v, masked=False), b,
+                    c.disc.jacobi_inverse(MASS, masked=False), rtol=1e-14, maxit=2000)
+        assert rel(host(x), xo) <= TOL
+    finally:
+        c.close()
+
+
+def test_vector_pcg_components_independent():
+    c = Case(6, 3, 3, 3, 2, seed=9, ncomp=3)
+    try:
+        B = c.vec(0) * (1 - c.mesh.boundary)[:, None]
+        x, st = c.op.pcg_solve(dev(B), maxit=6, fixed_iters=True)
+        X, _ = pcg(lambda v: c.disc.apply(STIFF, v), B, c.disc.jacobi_inverse(STIFF),
+                   maxit=6, fixed_iters=True)
+        assert rel(host(x), X) <= TOL
+    finally:
+        c.close()
+
+
+def test_mixed_precision_defect_correction():
+    c = Case(5, 4, 4, 4, 4, seed=10, fp32=True)
+    try:
+        b = manufactured_rhs(c)
+        x, st = c.op.pcg_solve_mixed(dev(b), outer_rtol=1e-10, inner_rtol=1e-5)
+        xg = host(x)
+        r = b - c.disc.apply(STIFF, xg)
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.2e-10
+        assert st["outer"] >= 2 and st["converged"]
+        x64, _ = mixed.solve_fp64(c.disc, b, 1e-12)
+        assert rel(xg, x64) < 1e-8
+    finally:
+        c.close()
+
+
+def test_grad_kappa_matches_oracle():
+    from oracle.geometry import quad_points
+    c = Case(5, 5, 3, 2, 2, seed=11, ncomp=2)
+    try:
+        kap = synth.kappa_log(quad_points(c.disc.rule, c.mesh.node_xyz), 3)
+        lam = c.vec(1) * (1 - c.mesh.boundary)[:, None]
+        u = c.vec(2) * (1 - c.mesh.boundary)[:, None]
+        g = host(c.op.grad_kappa(dev(lam), dev(u)))
+        ref = adjoint.grad_kappa(c.disc, lam, u)
+        assert rel(g, ref) <= TOL
+        # kappa-scaled operator
+        c.op.set_coeff(dev(kap))
+        c.disc.kappa = kap
+        w = host(c.op.apply(STIFF, dev(u)))
+        assert rel(w, c.disc.apply(STIFF, u)) <= TOL
+        assert rel(host(c.op.diag(STIFF)), c.disc.diag(STIFF)) <= TOL
+        c.op.set_coeff(None)
+        c.disc.kappa = None
+        assert rel(host(c.op.apply(STIFF, dev(u))), c.disc.apply(STIFF, u)) <= TOL
+    finally:
+        c.close()
+
+
+# ---- properties that hold at any size ------------------------------------
+def test_properties_symmetry_nullspace_volume():
+    c = Case(5, 6, 3, 3, 2, seed=12)
+    try:
+        u, v = c.vec(1), c.vec(2)
+        Au = host(c.op.apply(STIFF, dev(u)))
+        Av = host(c.op.apply(STIFF, dev(v)))
+        assert abs(v @ Au - u @ Av) <= 1e-13 * abs(v @ Au)
+        one = np.ones(c.disc.nglobal)
+        A1 = host(c.op.apply(STIFF, dev(one), masked=False))
+        assert np.abs(A1).max() <= 1e-13 * np.abs(host(c.op.diag(STIFF, masked=False))).max()
+        M1 = host(c.op.apply(MASS, dev(one), masked=False))
+        assert abs(M1.sum() - 1.0) <= 1e-13
+        X = c.mesh.global_coords()
+        for l in range(3):
+            AX = host(c.op.apply(STIFF, dev(X[:, l]), masked=False))
+            for m in range(3):
+                assert abs(X[:, m] @ AX - (l == m)) <= 1e-12
+    finally:
+        c.close()
+
+
+# ---- edge cases and errors -------------------------------------------------
+def test_single_element_and_zero_rhs():
+    c = Case(5, 7, 1, 1, 1, seed=13, dirichlet=False)
+    try:
+        u = c.vec(3)
+        assert rel(host(c.op.apply(STIFF, dev(u), masked=False)),
+                   c.disc.apply(STIFF, u, masked=False)) <= TOL
+    finally:
+        c.close()
+    c = Case(5, 3, 2, 2, 2, seed=13)
+    try:
+        x, st = c.op.pcg_solve(dev(np.zeros(c.disc.nglobal)), rtol=1e-8)
+        assert st["iters"] == 0 and np.all(host(x) == 0)
+        x, st = c.op.pcg_solve(dev(c.vec(1)), maxit=0)
+        assert st["iters"] == 0
+    finally:
+        c.close()
+
+
+def test_errors_are_reported():
+    import paper_2004_06722_amd.bp as B
+    from paper_2004_06722_amd import BpError
+    xi, _ = B.rule(4, B.GLL)
+    m = synth.brick_mesh(2, 1, 1, 3, xi, seed=None)
+    with pytest.raises(BpError, match="BP_ERR_ARG"):
+        B.Operator(3, 5, B.GLL, m.elem_dofs, m.node_xyz, m.nglobal)
+    bad = m.elem_dofs.copy()
+    bad[1, 5] = m.nglobal
+    with pytest.raises(BpError, match="BP_ERR_MESH"):
+        B.Operator(3, 4, B.GLL, bad, m.node_xyz, m.nglobal)
+    xyz = m.node_xyz.copy()
+    xyz[1, :, 0] = 1.5 - xyz[1, :, 0]
+    with pytest.raises(BpError, match="element 1"):
+        B.Operator(3, 4, B.GLL, m.elem_dofs, xyz, m.nglobal)
+    with pytest.raises(BpError, match="BP_ERR_ARG"):
+        B.Operator(9, 10, B.GLL, np.zeros((1, 1000), np.int64), np.zeros((1, 1000, 3)), 1000)
+    op = B.Operator(3, 4, B.GLL, m.elem_dofs, m.node_xyz, m.nglobal, m.boundary)
+    try:
+        b = np.zeros(m.nglobal)
+        b[np.nonzero(m.boundary == 0)[0][0]] = np.nan
+        with pytest.raises(BpError, match="NONFINITE"):
+            op.pcg_solve(dev(b))
+        with pytest.raises(BpError, match="FP32"):
+            op.apply(STIFF, dev(np.zeros(m.nglobal, np.float32)))
+    finally:
+        op.close()
