@@ -59,6 +59,18 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *out, in
     }
 }
 
+// Work-group barrier that also stops the instruction scheduler from moving
+// work across it. With one-wave work-groups the compiler drops s_barrier
+// (LDS accesses of a wave are ordered), and without the scheduling fence it
+// would hoist the LDS reads of every plane at once and run out of registers.
+// The memory clobber also makes the compiler re-read the lane-dependent
+// rows of D^ from LDS in every plane instead of keeping them all live.
+__device__ __forceinline__ void plane_sync() {
+  __syncthreads();
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // Decoded gather index: global id, or -1 when the node is skipped
 // (element slot not live, or a Dirichlet node under the mask).
 __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
@@ -70,64 +82,95 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // ---------------------------------------------------------------------------
 // BK5/BK6: stiffness with collocated GLL quadrature (J^ = I, q = p1).
 // NC components share every load of G and of the gather map.
+//
+// The kernel is bound by HBM latency more than by arithmetic, so it is laid
+// out to need few dependent round trips: each lane requests its whole column
+// of G (6 x p1 values, GPRE planes of them at entry when GPRE = p1) and of
+// the gather map at once, then gathers u, then computes from registers and
+// LDS. The k direction stays in registers; the r and s contractions go
+// through LDS tiles. Loads are branch-free: an element slot past the end
+// reads the last element and a Dirichlet node reads its (valid) global
+// entry, both scaled by a 0/1 mask. Entries of D^ with compile-time indices
+// are scalar loads from Dg (global memory, D^[a][m] at a * p1 + m); the
+// lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
+// accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
 // ---------------------------------------------------------------------------
 template <int P1, int NC, typename T>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
-    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
-    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp,
-    int c0, int masked, double *__restrict__ part, const int *__restrict__ done) {
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *Dg,
+    const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0, int masked,
+    double *__restrict__ part, const int *__restrict__ done) {
   using PL = Plane<P1, P1>;
-  constexpr int N3 = P1 * P1 * P1, PAD = P1 + 1;
+  constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
   if (done && *done) return;
-  __shared__ T sD[P1][P1];
-  __shared__ T su[PL::EPB][NC][P1][P1][PAD];
-  __shared__ T sr[PL::EPB][NC][P1][P1][PAD];
-  __shared__ T ss[PL::EPB][NC][P1][P1][PAD];
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
   const int slot = act ? t / PL::N : 0;
   const int ij = t % PL::N;
   const int i = ij % P1, j = ij / P1;
   const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
+  if (PL::EPB == 1 && e >= nelem) return;  // uniform over the work-group
   const bool live = act && e < nelem;
-  for (int x = t; x < P1 * P1; x += PL::THREADS) sD[x / P1][x % P1] = basis[P1 * P1 + x];
+  const int64_t ec = live ? e : nelem - 1;  // element whose data a lane reads
 
-  T ru[NC][P1];
+  __shared__ T sD[P1][PAD];   // sD[a][m]  = D^[a][m]
+  __shared__ T sDt[P1][PAD];  // sDt[m][a] = D^[a][m]
+  __shared__ T su[PL::EPB][NC][P1][P1][PAD];
+  __shared__ T sr[PL::EPB][NC][P1][P1][PAD];
+  __shared__ T ss[PL::EPB][NC][P1][P1][PAD];
+  // one round trip: the column of the gather map and of G
+  const int32_t *ie = idx + ec * N3 + ij;
+  const T *Ge = G + ec * 6 * N3 + ij;
   int gk[P1];
+  T g[6][P1];
+#pragma unroll
+  for (int k = 0; k < P1; ++k) gk[k] = __builtin_nontemporal_load(ie + k * PP);
+#pragma unroll
+  for (int k = 0; k < P1; ++k)
+#pragma unroll
+    for (int n = 0; n < 6; ++n) g[n][k] = __builtin_nontemporal_load(Ge + n * N3 + k * PP);
+
+  // decode: global id and 0/1 mask (0 for dead slots and masked Dirichlet)
+  T mk[P1];
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
-    const int l = i + P1 * (j + P1 * k);
-    const int v = live ? __builtin_nontemporal_load(idx + e * N3 + l) : -1;
-    gk[k] = decode_index(v, live, masked);
+    const int v = gk[k];
+    mk[k] = (live && (v >= 0 || !masked)) ? T(1) : T(0);
+    gk[k] = v >= 0 ? v : -1 - v;
+  }
+
+  // gather u (requested before D^ is staged, so both wait together)
+  T ru[NC][P1];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const T val = gk[k] >= 0 ? u[(int64_t)gk[k] * ncomp + c0 + c] : T(0);
-      ru[c][k] = val;
-      if (act) su[slot][c][k][j][i] = val;
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int k = 0; k < P1; ++k) ru[c][k] = u[(int64_t)gk[k] * ncomp + c0 + c] * mk[k];
+  for (int x = t; x < PP; x += PL::THREADS) {
+    sD[x / P1][x % P1] = Dg[x];
+    sDt[x % P1][x / P1] = Dg[x];
+  }
+
+  // u into LDS; derivative along t (k) in registers
+  T rt[NC][P1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      if (act) su[slot][c][k][j][i] = ru[c][k];
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < P1; ++m) s += Dg[k * P1 + m] * ru[c][m];
+      rt[c][k] = s;
     }
   }
   __syncthreads();
 
-  // derivative along t (k): thread-local
-  T rt[NC][P1];
+  // derivatives along r, s through LDS; apply G; energy at the points
+  double en[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < P1; ++m) s += sD[k][m] * ru[c][m];
-      rt[c][k] = s;
-    }
-
-  // derivatives along r, s through LDS; apply G (6 symmetric components)
-  const T *Ge = G + (live ? e : 0) * 6 * N3 + ij;
+  for (int c = 0; c < NC; ++c) en[c] = 0.0;
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
-    T g[6];
-#pragma unroll
-    for (int n = 0; n < 6; ++n)
-      g[n] = live ? __builtin_nontemporal_load(Ge + n * N3 + k * P1 * P1) : T(0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T ur = 0, us = 0;
@@ -137,22 +180,20 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
         us += sD[j][m] * su[slot][c][k][m][i];
       }
       const T ut = rt[c][k];
-      const T vr = g[0] * ur + g[1] * us + g[2] * ut;
-      const T vs = g[1] * ur + g[3] * us + g[4] * ut;
-      const T vt = g[2] * ur + g[4] * us + g[5] * ut;
+      const T vr = g[0][k] * ur + g[1][k] * us + g[2][k] * ut;
+      const T vs = g[1][k] * ur + g[3][k] * us + g[4][k] * ut;
+      const T vt = g[2][k] * ur + g[4][k] * us + g[5][k] * ut;
+      en[c] += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
+      rt[c][k] = vt;
       if (act) {
         sr[slot][c][k][j][i] = vr;
         ss[slot][c][k][j][i] = vs;
       }
-      rt[c][k] = vt;
     }
   }
   __syncthreads();
 
-  // transposed derivatives, energy and scatter
-  double en[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) en[c] = 0.0;
+  // transposed derivatives and scatter
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
 #pragma unroll
@@ -160,12 +201,11 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
       T acc = 0;
 #pragma unroll
       for (int m = 0; m < P1; ++m) {
-        acc += sD[m][k] * rt[c][m];
-        acc += sD[m][i] * sr[slot][c][k][j][m];
-        acc += sD[m][j] * ss[slot][c][k][m][i];
+        acc += Dg[m * P1 + k] * rt[c][m];
+        acc += sDt[i][m] * sr[slot][c][k][j][m];
+        acc += sDt[j][m] * ss[slot][c][k][m][i];
       }
-      en[c] += (double)ru[c][k] * (double)acc;
-      if (gk[k] >= 0) atomic_add(w + (int64_t)gk[k] * ncomp + c0 + c, acc);
+      if (mk[k] != T(0)) atomic_add(w + (int64_t)gk[k] * ncomp + c0 + c, acc);
     }
   }
   if (part) block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0, 1);

@@ -24,17 +24,18 @@ int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *u, T *w
                  double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
   const int64_t nb = apply_blocks(op);
+  const T *Dg = basis + P1 * P1;  // D^ follows J^ (both p1 x p1 here)
   for (int c0 = 0; c0 < op->ncomp;) {
     const int g = op->ncomp - c0 >= 3 ? 3 : op->ncomp - c0;
     if (g == 3)
       hipLaunchKernelGGL((k_stiff_colloc<P1, 3, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
-                         op->idx, G, basis, u, w, op->ncomp, c0, masked, part, done);
+                         op->idx, G, Dg, u, w, op->ncomp, c0, masked, part, done);
     else if (g == 2)
       hipLaunchKernelGGL((k_stiff_colloc<P1, 2, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
-                         op->idx, G, basis, u, w, op->ncomp, c0, masked, part, done);
+                         op->idx, G, Dg, u, w, op->ncomp, c0, masked, part, done);
     else
       hipLaunchKernelGGL((k_stiff_colloc<P1, 1, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
-                         op->idx, G, basis, u, w, op->ncomp, c0, masked, part, done);
+                         op->idx, G, Dg, u, w, op->ncomp, c0, masked, part, done);
     c0 += g;
   }
   return BP_OK;

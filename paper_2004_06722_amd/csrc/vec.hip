@@ -46,8 +46,17 @@ __device__ void reduce_columns(const double *__restrict__ part, int64_t nb, int 
                                double *res) {
   __shared__ double sh[kFinThreads];
   for (int col = 0; col < width; ++col) {
+    // rows t, t + 1024, ... in order; eight loads in flight per step
     double s = 0.0;
-    for (int64_t r = threadIdx.x; r < nb; r += kFinThreads) s += part[r * width + col];
+    int64_t r = threadIdx.x;
+    for (; r + 7 * kFinThreads < nb; r += 8 * kFinThreads) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(r + q * kFinThreads) * width + col];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += v[q];
+    }
+    for (; r < nb; r += kFinThreads) s += part[r * width + col];
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int h = kFinThreads / 2; h > 0; h >>= 1) {
