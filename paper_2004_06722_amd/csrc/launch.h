@@ -16,9 +16,15 @@ int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, dou
                       hipStream_t s);
 
 // vector kernels (vec.hip); sizes are global nodes n and components nc
+// CG vector kernels run one node per thread (vec_blocks); fills and
+// conversions use a capped grid-stride grid (grid_blocks). Block partial
+// sums are reduced to at most kStage2Rows rows before the final fixed-order
+// single-work-group sum; the stage-1 output sits right after the partials.
 constexpr int kVecThreads = 256;
 constexpr int64_t kVecMaxBlocks = 2048;
+constexpr int64_t kStage2Rows = 256;
 int64_t vec_blocks(int64_t n);
+int64_t grid_blocks(int64_t n);
 void fill_f64(double *x, int64_t n, double v, hipStream_t s);
 void fill_f32(float *x, int64_t n, float v, hipStream_t s);
 void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,

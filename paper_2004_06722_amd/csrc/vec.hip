@@ -68,6 +68,36 @@ __device__ void reduce_columns(const double *__restrict__ part, int64_t nb, int 
   }
 }
 
+// Stage 1 of the fixed-order reduction: work-group b adds rows
+// [b * chunk, (b + 1) * chunk) of part[nb][width] into out[b][width].
+__global__ __launch_bounds__(kVecThreads) void k_reduce_rows(const double *__restrict__ part,
+                                                             int64_t nb, int width, int64_t chunk,
+                                                             double *__restrict__ out) {
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < nb ? r0 + chunk : nb;
+  __shared__ double sh[kVecThreads];
+  for (int col = 0; col < width; ++col) {
+    double s = 0.0;
+    int64_t r = r0 + threadIdx.x;
+    for (; r + 3 * kVecThreads < r1; r += 4 * kVecThreads) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = part[(r + q * kVecThreads) * width + col];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s += v[q];
+    }
+    for (; r < r1; r += kVecThreads) s += part[r * width + col];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kVecThreads / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * width + col] = sh[0];
+    __syncthreads();
+  }
+}
+
 __device__ __forceinline__ bool converged(const DevScalars *sc, int nc) {
   bool ok = true;
   for (int c = 0; c < nc; ++c) {
@@ -95,8 +125,8 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_init(int64_t n, const T *__r
   double rz[NC], rr[NC], bb[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) rz[c] = rr[c] = bb[c] = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kVecThreads) {
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v < n) {
     const T di = dinv[v];
     // dinv = 0 exactly on Dirichlet nodes: b is read as 0 there
     const bool free = di != T(0);
@@ -167,8 +197,8 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xr(
     al[c] = (T)sc->alpha[c];
     rz[c] = rr[c] = 0.0;
   }
-  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kVecThreads) {
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v < n) {
     const T di = dinv[v];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -213,8 +243,8 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_p(int64_t n, T *__res
   T be[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) be[c] = (T)sc->beta[c];
-  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kVecThreads) {
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v < n) {
     const T di = dinv[v];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -233,8 +263,8 @@ __global__ __launch_bounds__(kVecThreads) void k_dc_residual(int64_t n, const do
   double rr[NC], bb[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) rr[c] = bb[c] = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * kVecThreads) {
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v < n) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int64_t o = v * NC + c;
@@ -306,26 +336,47 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_geometry(const double *__
 }  // namespace
 
 int64_t vec_blocks(int64_t n) {
+  const int64_t b = (n + kVecThreads - 1) / kVecThreads;
+  return b < 1 ? 1 : b;
+}
+
+int64_t grid_blocks(int64_t n) {
   int64_t b = (n + kVecThreads - 1) / kVecThreads;
   if (b > kVecMaxBlocks) b = kVecMaxBlocks;
   return b < 1 ? 1 : b;
 }
 
+// Reduce part[nb][width] to at most kStage2Rows rows in `stage`, then return
+// the pointer and row count the single-work-group finisher reads.
+static const double *reduce_stage1(const double *part, int64_t nb, int width, double *stage,
+                                   int64_t *rows, hipStream_t s) {
+  if (nb <= kStage2Rows) {
+    *rows = nb;
+    return part;
+  }
+  const int64_t chunk = (nb + kStage2Rows - 1) / kStage2Rows;
+  const int64_t blocks = (nb + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(blocks), dim3(kVecThreads), 0, s, part, nb, width, chunk,
+                     stage);
+  *rows = blocks;
+  return stage;
+}
+
 void fill_f64(double *x, int64_t n, double v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<double>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, x, n, v);
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, x, n, v);
 }
 void fill_f32(float *x, int64_t n, float v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<float>, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, x, n, v);
+  hipLaunchKernelGGL(k_fill<float>, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, x, n, v);
 }
 void to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f32, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, src, dst, n);
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, src, dst, n);
 }
 void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_invert, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, d, dinv, dinv32, n);
+  hipLaunchKernelGGL(k_invert, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, d, dinv, dinv32, n);
 }
 void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,
                     int64_t nelem, int nq, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_geometry, dim3(vec_blocks(nelem * 6 * nq)), dim3(kVecThreads), 0, s,
+  hipLaunchKernelGGL(k_scale_geometry, dim3(grid_blocks(nelem * 6 * nq)), dim3(kVecThreads), 0, s,
                      G, kappa, Gk, Gk32, nelem, nq);
 }
 
@@ -349,11 +400,15 @@ void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, dou
   hipLaunchKernelGGL((k_cg_init<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, b, r, w, p, dinv, part)
   BP_NC_SWITCH(nc, L)
 #undef L
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+  int64_t rows = 0;
+  const double *src = reduce_stage1(part, nb, 3 * nc, part + nb * 3 * nc, &rows, s);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
 }
 
 void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+  int64_t rows = 0;
+  const double *src = reduce_stage1(part, nb, nc, const_cast<double *>(part) + nb * nc, &rows, s);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
 }
 
 template <typename T>
@@ -368,7 +423,10 @@ void cg_update_xr(int nc, int64_t n, T *x, const T *p, T *r, T *w, const T *dinv
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+  int64_t rows = 0;
+  const double *src =
+      reduce_stage1(part, nb, 2 * nc, const_cast<double *>(part) + nb * 2 * nc, &rows, s);
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
 }
 
 template <typename T>
@@ -388,11 +446,13 @@ void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, doubl
   hipLaunchKernelGGL((k_dc_residual<NC>), dim3(nb), dim3(kVecThreads), 0, s, n, b, r, w, part)
   BP_NC_SWITCH(nc, L)
 #undef L
-  hipLaunchKernelGGL(k_fin_norms, dim3(1), dim3(kFinThreads), 0, s, part, nb, nc, sc);
+  int64_t rows = 0;
+  const double *src = reduce_stage1(part, nb, 2 * nc, part + nb * 2 * nc, &rows, s);
+  hipLaunchKernelGGL(k_fin_norms, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
 }
 
 void dc_accumulate(int64_t n, double *x, const float *d, hipStream_t s) {
-  hipLaunchKernelGGL(k_accumulate, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, x, d, n);
+  hipLaunchKernelGGL(k_accumulate, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, x, d, n);
 }
 
 template void cg_init<double>(int, int64_t, const double *, double *, double *, double *,
