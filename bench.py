@@ -6,7 +6,7 @@ right-hand side (seed 0), Jacobi-PCG with a fixed iteration count (the
 paper's timing mode). One step = one CG iteration: operator apply with
 gather/scatter, the two fused vector updates and their reductions.
 
-python bench.py [--gpus 1] [--steps 100] [--warmup 20] [--sweep] [--no-cpu]
+python bench.py [--gpus 1] [--steps 100] [--warmup 20] [--no-sweep] [--no-cpu]
 
 Prints one JSON line (rank 0). DOFs/s = iterations * n / seconds with
 n = N^3 E (section 2); the unique-node count is reported beside it.
@@ -96,6 +96,44 @@ def cpu_baseline(N: int, target_s: float = 15.0):
                       f"{os.cpu_count()} logical CPUs visible"}
 
 
+def kernel_source_hash() -> str:
+    """Hash of the device sources the traffic counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "ops.hip"):
+        with open(os.path.join(ROOT, "paper_2004_06722_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if it is missing or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "bk5_p7_e64cube_hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def calib_copy():
+    """Plain device copy of known size (2 GiB read + 2 GiB written, 3 times),
+    the reference for scaling the HBM byte counters."""
+    import torch
+    n = 1 << 28
+    a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"calib-copy: {n * 8} bytes read and written per launch, 3 launches")
+
+
 def n08_from_sweep(points):
     """r_max, n_0.8 (log-interpolated first crossing of 0.8 r_max), t_0.8."""
     pts = sorted(points)
@@ -119,10 +157,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--N", type=int, default=7)
     ap.add_argument("--k", type=int, default=18, help="E = 2^k elements (default 64^3)")
-    ap.add_argument("--sweep", action="store_true", help="E = 2^k sweep for n_0.8")
-    ap.add_argument("--sweep-k", default="5:18")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the E = 2^k sweep for n_0.8")
+    ap.add_argument("--sweep-k", default="5:17", help="sweep E = 2^k for k in lo:hi")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true", help="run only the counter calibration copy")
     args = ap.parse_args()
+    if args.calib_copy:
+        calib_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU decomposition is described but not built.", file=sys.stderr)
@@ -149,6 +191,7 @@ def main():
     ab = model.apply_bytes(bp, N, E)
     achieved = ab / (apply_avg_ms * 1e-3) / 1e9
     it_bytes = model.iteration_bytes(bp, N, E)
+    kname = f"k_stiff_colloc<{N + 1}, 1, double>"
     loop_s = st["ms"] * 1e-3
     result = {
         "metric": METRIC,
@@ -167,9 +210,9 @@ def main():
                                f"{info['grid'][1]}x{info['grid'][2]}, Jacobi-PCG fixed "
                                f"{args.steps} iterations",
                    "N": N, "E": E, "n": n, "n_unique": info["n_unique"]},
-        "roofline": {"bound": "hbm", "kernel": f"k_stiff_colloc<{N + 1},1,double>",
+        "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": model.HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / model.HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / model.HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                      "bytes_per_launch": ab, "avg_launch_ms": apply_avg_ms},
         "iteration": {"algorithmic_GBs": it_bytes * args.steps / loop_s / 1e9,
                       "frac_hbm": it_bytes * args.steps / loop_s / 1e9 / model.HBM_PEAK_GBS,
@@ -181,10 +224,10 @@ def main():
     del b
     torch.cuda.empty_cache()
 
-    if args.sweep:
+    if not args.no_sweep:
         lo, hi = (int(x) for x in args.sweep_k.split(":"))
-        pts = []
-        for kk in range(lo, hi + 1):
+        pts = [(n, value)]
+        for kk in range(lo, min(hi, k - 1) + 1):
             o2, b2, inf2 = build_problem(bp, N, kk)
             w2, st2 = time_solve(o2, b2, 100, 10)
             r = 100 * inf2["n"] / w2
@@ -193,8 +236,10 @@ def main():
             o2.close()
             del b2
         rmax, n08, t08 = n08_from_sweep(pts)
-        result["sweep"] = {"points": [[a, b_] for a, b_ in pts], "r_max": rmax, "n_0.8": n08,
-                           "t_0.8_s": t08}
+        result["sweep"] = {"points": [[a, b_] for a, b_ in sorted(pts)], "r_max": rmax,
+                           "n_0.8": n08, "t_0.8_s": t08,
+                           "note": "BP5 N=7, E=2^k, 100 iterations each; n = N^3 E; n_0.8 is "
+                                   "log-interpolated where DOFs/s first reaches 0.8 r_max"}
     if not args.no_cpu:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(N)
