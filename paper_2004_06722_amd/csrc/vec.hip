@@ -1,9 +1,9 @@
-// Streaming vector kernels of the Jacobi-PCG iteration (section 3; the
-// vector operations are the "n or 2n flops, one or two words per operation"
-// updates of section 8) with deterministic reductions: every work-group
-// writes its partial sums, and a single work-group adds the partials in a
-// fixed order and updates alpha, beta and the convergence flag on the
-// device, so the host never waits inside the iteration.
+// Streaming vector kernels of the Jacobi-PCG iteration (section 3; section 8
+// counts these updates as a few flops and memory words per DOF each) with
+// deterministic reductions: every work-group writes its partial sums, a
+// first stage folds them to at most 256 rows and a single work-group adds
+// those in a fixed order and updates alpha, beta and the convergence flag on
+// the device, so the host never waits inside the iteration.
 #include <cmath>
 
 #include "bp_internal.h"

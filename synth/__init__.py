@@ -15,11 +15,12 @@ Conventions (paper section 4, eq. (xijk)/(uijk)): a node of element e is
 are numbered lexicographically (x fastest); global nodes are numbered
 lexicographically on the (p*Ex+1) x (p*Ey+1) x (p*Ez+1) lattice.
 """
-from .mesh import (element_grid, BrickMesh, brick_mesh, vertex_perturbation,
-                   trilinear_nodes)
+from .mesh import (element_grid, BrickMesh, brick_mesh, element_coordinates,
+                   vertex_perturbation, trilinear_nodes)
 from .fields import (rhs_uniform, manufactured_u, manufactured_f, kappa_log,
                      fd_direction)
 
-__all__ = ["element_grid", "BrickMesh", "brick_mesh", "vertex_perturbation",
+__all__ = ["element_grid", "BrickMesh", "brick_mesh", "element_coordinates",
+           "vertex_perturbation",
            "trilinear_nodes", "rhs_uniform", "manufactured_u", "manufactured_f",
            "kappa_log", "fd_direction"]

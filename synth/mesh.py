@@ -97,6 +97,39 @@ class BrickMesh:
         return out
 
 
+def _grid_vertices(ex, ey, ez, seed, amplitude):
+    gx = np.linspace(0.0, 1.0, ex + 1)
+    gy = np.linspace(0.0, 1.0, ey + 1)
+    gz = np.linspace(0.0, 1.0, ez + 1)
+    Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
+    verts = np.stack([X, Y, Z], axis=-1)                 # [ez+1, ey+1, ex+1, 3]
+    if seed is not None:
+        h = 1.0 / max(ex, ey, ez)
+        verts = verts + vertex_perturbation(verts, h, seed, amplitude)
+    return verts
+
+
+def _element_nodes(verts, ex, ey, elems, ref_nodes):
+    ix, iy, iz = elems % ex, (elems // ex) % ey, elems // (ex * ey)
+    corners = np.empty((elems.size, 2, 2, 2, 3))
+    for cz in range(2):
+        for cy in range(2):
+            for cx in range(2):
+                corners[:, cz, cy, cx] = verts[iz + cz, iy + cy, ix + cx]
+    return trilinear_nodes(corners, ref_nodes)
+
+
+def element_coordinates(ex: int, ey: int, ez: int, p: int, ref_nodes: np.ndarray,
+                        elements: np.ndarray, seed: int | None = 0,
+                        amplitude: float = 0.1) -> np.ndarray:
+    """node_xyz [len(elements), p1^3, 3] of the listed elements of brick_mesh."""
+    ref_nodes = np.asarray(ref_nodes, dtype=np.float64)
+    if ref_nodes.shape != (p + 1,):
+        raise ValueError("ref_nodes must hold p+1 positions")
+    verts = _grid_vertices(ex, ey, ez, seed, amplitude)
+    return _element_nodes(verts, ex, ey, np.asarray(elements, dtype=np.int64), ref_nodes)
+
+
 def brick_mesh(ex: int, ey: int, ez: int, p: int, ref_nodes: np.ndarray,
                seed: int | None = 0, amplitude: float = 0.1,
                chunk: int = 16384) -> BrickMesh:
@@ -114,15 +147,7 @@ def brick_mesh(ex: int, ey: int, ez: int, p: int, ref_nodes: np.ndarray,
     nglobal = nx * ny * nz
     E = ex * ey * ez
 
-    # vertices of the element grid, perturbed
-    gx = np.linspace(0.0, 1.0, ex + 1)
-    gy = np.linspace(0.0, 1.0, ey + 1)
-    gz = np.linspace(0.0, 1.0, ez + 1)
-    Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
-    verts = np.stack([X, Y, Z], axis=-1)                 # [ez+1, ey+1, ex+1, 3]
-    if seed is not None:
-        h = 1.0 / max(ex, ey, ez)
-        verts = verts + vertex_perturbation(verts, h, seed, amplitude)
+    verts = _grid_vertices(ex, ey, ez, seed, amplitude)
 
     # global numbering: base of element + offset of local node
     e = np.arange(E, dtype=np.int64)
@@ -135,14 +160,7 @@ def brick_mesh(ex: int, ey: int, ez: int, p: int, ref_nodes: np.ndarray,
 
     node_xyz = np.empty((E, p1 ** 3, 3))
     for s in range(0, E, chunk):
-        ee = e[s:s + chunk]
-        ix, iy, iz = ee % ex, (ee // ex) % ey, ee // (ex * ey)
-        corners = np.empty((ee.size, 2, 2, 2, 3))
-        for cz in range(2):
-            for cy in range(2):
-                for cx in range(2):
-                    corners[:, cz, cy, cx] = verts[iz + cz, iy + cy, ix + cx]
-        node_xyz[s:s + chunk] = trilinear_nodes(corners, ref_nodes)
+        node_xyz[s:s + chunk] = _element_nodes(verts, ex, ey, e[s:s + chunk], ref_nodes)
 
     I = np.arange(nglobal, dtype=np.int64)
     gi, gj, gk = I % nx, (I // nx) % ny, I // (nx * ny)

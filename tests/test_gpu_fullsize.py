@@ -1,0 +1,126 @@
+"""GPU parity at the full sizes of the benchmark configurations.
+
+The oracle computes selected outputs one by one (the elements around sample
+nodes), and properties that hold at any size are checked on the whole
+result. Inputs come from synth only.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.operators import MASS, STIFF
+from oracle.quadrature import bp_rule
+from oracle.sampled import apply_at_nodes, elements_containing
+from tests.gpu_cases import TOL, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def build(bp, N, k, ncomp=1, fp32=False):
+    import paper_2004_06722_amd.bp as B
+    q, quad = B.bp_quadrature(bp, N)
+    ex, ey, ez = synth.element_grid(k) if isinstance(k, int) else k
+    xi, _ = B.rule(N + 1, B.GLL)
+    mesh = synth.brick_mesh(ex, ey, ez, N, xi, seed=0)
+    dirich = mesh.boundary if bp >= 3 else None
+    op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp,
+                    fp32=fp32)
+    return op, mesh, (ex, ey, ez), dirich
+
+
+def sample_nodes(mesh, count, seed):
+    rng = np.random.default_rng(seed)
+    inner = np.nonzero(mesh.boundary == 0)[0]
+    nodes = np.concatenate([rng.choice(inner, count, replace=False),
+                            rng.choice(mesh.nglobal, 8, replace=False)])
+    return np.unique(nodes)
+
+
+def sampled_check(bp, N, k, ncomp=1, which=STIFF, count=48):
+    op, mesh, grid, dirich = build(bp, N, k, ncomp)
+    try:
+        u = synth.rhs_uniform(mesh.nglobal, 11, ncomp=ncomp)
+        w = op.apply(which, torch.from_numpy(u).cuda(), masked=dirich is not None)
+        nodes = sample_nodes(mesh, count, 5)
+        wg = w[torch.from_numpy(nodes).cuda()].cpu().numpy()
+        rule = bp_rule(bp, N)
+        els = elements_containing(mesh.elem_dofs, nodes)
+        xyz = synth.element_coordinates(*grid, N, rule.xi, els, seed=0)
+        wo = apply_at_nodes(rule, mesh.elem_dofs[els], xyz, u, nodes, which,
+                            dirich is not None, dirich)
+        assert rel(wg, wo) <= TOL, rel(wg, wo)
+        return op, mesh
+    except Exception:
+        op.close()
+        raise
+
+
+def test_bp5_n7_e64cube_sampled_and_energy_identity():
+    op, mesh = sampled_check(5, 7, 18)
+    try:
+        # X^T A X = I for the coordinate fields (unmasked), on the whole mesh
+        X = torch.from_numpy(mesh.global_coords()).cuda()
+        for l in range(3):
+            AX = op.apply(STIFF, X[:, l].contiguous(), masked=False)
+            for m in range(3):
+                v = torch.dot(X[:, m], AX).item()
+                assert abs(v - (l == m)) <= 1e-11, (l, m, v)
+    finally:
+        op.close()
+
+
+def test_bp6_n7_e48cube_vector_sampled():
+    op, _ = sampled_check(6, 7, (48, 48, 48), ncomp=3)
+    op.close()
+
+
+@pytest.mark.parametrize("bp,N,k", [(3, 7, 15), (1, 7, 15), (3, 3, 18), (1, 2, 20)])
+def test_bp1_bp3_sampled(bp, N, k):
+    op, _ = sampled_check(bp, N, k, which=MASS if bp == 1 else STIFF)
+    op.close()
+
+
+def test_mixed_precision_e64cube_manufactured():
+    import paper_2004_06722_amd.bp as B
+    op, mesh, grid, dirich = build(5, 7, 18, fp32=True)
+    try:
+        xyz = torch.from_numpy(mesh.global_coords()).cuda()
+        f = (3 * np.pi ** 2 * torch.sin(np.pi * xyz[:, 0]) * torch.sin(np.pi * xyz[:, 1])
+             * torch.sin(np.pi * xyz[:, 2])).contiguous()
+        b = op.apply(MASS, f, masked=False) * torch.from_numpy(1.0 - mesh.boundary).cuda()
+        xm, stm = op.pcg_solve_mixed(b, outer_rtol=1e-10, inner_rtol=1e-5)
+        x64, st64 = op.pcg_solve(b, rtol=1e-10, maxit=20000)
+        assert stm["converged"] and st64["converged"]
+        assert stm["rel_res"][0] <= 1e-10
+        ue = (torch.sin(np.pi * xyz[:, 0]) * torch.sin(np.pi * xyz[:, 1])
+              * torch.sin(np.pi * xyz[:, 2]))
+        err_m = (xm - ue).abs().max().item()
+        err_64 = (x64 - ue).abs().max().item()
+        # N=7 on 64^3 elements: the discretisation error is far below the
+        # algebraic one; both solves stop at 1e-10 relative residual.
+        assert err_m < 1e-7 and err_64 < 1e-7, (err_m, err_64)
+        assert (xm - x64).norm().item() / x64.norm().item() < 1e-8
+    finally:
+        op.close()
+
+
+def test_grad_kappa_n5_e32cube_sampled():
+    from oracle.adjoint import grad_kappa
+    from oracle.operators import Discretization
+    op, mesh, grid, dirich = build(5, 5, 15, ncomp=8)
+    try:
+        lam = synth.rhs_uniform(mesh.nglobal, 200, ncomp=8, dirichlet=mesh.boundary)
+        u = synth.rhs_uniform(mesh.nglobal, 300, ncomp=8, dirichlet=mesh.boundary)
+        g = op.grad_kappa(torch.from_numpy(lam).cuda(), torch.from_numpy(u).cuda())
+        els = np.unique(np.random.default_rng(3).choice(mesh.elem_dofs.shape[0], 24, replace=False))
+        gg = g[torch.from_numpy(els).cuda()].cpu().numpy()
+        rule = bp_rule(5, 5)
+        xyz = synth.element_coordinates(*grid, 5, rule.xi, els, seed=0)
+        sub = mesh.elem_dofs[els]
+        uniq, inv = np.unique(sub, return_inverse=True)
+        disc = Discretization(rule, inv.reshape(sub.shape), xyz, uniq.size, mesh.boundary[uniq])
+        go = grad_kappa(disc, lam[uniq], u[uniq])
+        assert rel(gg, go) <= TOL
+    finally:
+        op.close()

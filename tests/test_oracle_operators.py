@@ -174,3 +174,17 @@ def test_inverted_element_is_rejected():
     xyz[1, :, 0] = 1.5 - xyz[1, :, 0]      # mirror element 1 in x
     with pytest.raises(ValueError, match="element 1"):
         geometric_factors(rule, xyz)
+
+
+def test_sampled_apply_equals_full_apply():
+    from oracle.sampled import apply_at_nodes, elements_containing
+    disc, mesh = make_disc(5, 3, 4, 3, 3, seed=12)
+    u = np.random.default_rng(14).standard_normal((disc.nglobal, 2))
+    full = disc.apply(STIFF, u)
+    nodes = np.array([0, 5, 77, 300, disc.nglobal // 2, disc.nglobal - 1])
+    els = elements_containing(mesh.elem_dofs, nodes)
+    xyz = synth.element_coordinates(4, 3, 3, 3, disc.rule.xi, els, seed=12)
+    assert np.array_equal(xyz, mesh.node_xyz[els])
+    w = apply_at_nodes(disc.rule, mesh.elem_dofs[els], xyz, u, nodes, STIFF, True,
+                       mesh.boundary)
+    assert rel_err(w, full[nodes]) < 1e-14
