@@ -39,13 +39,13 @@ def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0):
     import synth
     import paper_2004_06722_amd.bp as B
     q, quad = B.bp_quadrature(bp, N)
-    ex, ey, ez = synth.element_grid(k)
+    ex, ey, ez = synth.element_grid(k) if isinstance(k, int) else k
     xi, _ = B.rule(N + 1, B.GLL)
     mesh = synth.brick_mesh(ex, ey, ez, N, xi, seed=0)
     dirich = mesh.boundary if bp >= 3 else None
     op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp)
     b = synth.rhs_uniform(mesh.nglobal, seed, ncomp=ncomp, dirichlet=dirich)
-    bd = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()     # component-major
     info = {"E": ex * ey * ez, "grid": [ex, ey, ez], "n": N ** 3 * ex * ey * ez,
             "n_unique": int(mesh.nglobal)}
     del mesh
@@ -150,6 +150,211 @@ def n08_from_sweep(points):
     return rmax, n08, (1.25 * n08 / rmax if n08 else None)
 
 
+# ---------------------------------------------------------------------------
+# secondary workloads (one JSON line each); the default run is the BP5 line
+# ---------------------------------------------------------------------------
+def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0):
+    """Fixed-iteration PCG on BPj; returns (record dict, operator kernel avg ms)."""
+    import torch
+
+    from paper_2004_06722_amd import model
+    from paper_2004_06722_amd._lib import BP_OPT_TIME_APPLY
+    op, b, info = build_problem(bp, N, grid, ncomp=ncomp, seed=seed)
+    op.set_option(BP_OPT_TIME_APPLY, 1)
+    which = 1 if bp in (1, 2) else 3
+    if warmup:
+        op.pcg_solve(b, which=which, maxit=warmup, fixed_iters=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = op.pcg_solve(b, which=which, maxit=steps, fixed_iters=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    op.close()
+    E, n = info["E"], info["n"]
+    log(f"BP{bp} N={N} E={E} ncomp={ncomp}: {steps} iterations in {wall * 1e3:.1f} ms")
+    apply_ms = st["apply_ms"] / max(st["apply_count"], 1)
+    ab = model.apply_bytes(bp, N, E, ncomp)
+    return {"bp": bp, "N": N, "E": E, "ncomp": ncomp, "n": n, "n_unique": info["n_unique"],
+            "iters": steps, "wall_ms": wall * 1e3, "ms_per_iter": wall * 1e3 / steps,
+            "DOFs_per_s": steps * n * ncomp / wall,
+            "apply_avg_ms": apply_ms, "apply_alg_GBs": ab / (apply_ms * 1e-3) / 1e9,
+            "apply_frac_hbm": ab / (apply_ms * 1e-3) / 1e9 / model.HBM_PEAK_GBS,
+            "iter_alg_frac_hbm": model.iteration_bytes(bp, N, E, ncomp) * steps
+                                 / (st["ms"] * 1e-3) / 1e9 / model.HBM_PEAK_GBS}
+
+
+def workload_vector(args):
+    """BP2/BP4/BP6 (3 components) against BP1/BP3/BP5 on the same mesh."""
+    grid = (48, 48, 48)
+    rows = []
+    for sbp, vbp in ((1, 2), (3, 4), (5, 6)):
+        s_rec = run_fixed(sbp, 7, grid, 1)
+        log(f"BP{sbp}: {s_rec['DOFs_per_s']:.3e} DOFs/s")
+        v_rec = run_fixed(vbp, 7, grid, 3, seed=0)
+        log(f"BP{vbp}: {v_rec['DOFs_per_s']:.3e} DOFs/s (3 components)")
+        v_rec["ratio_vs_scalar"] = v_rec["DOFs_per_s"] / s_rec["DOFs_per_s"]
+        rows += [s_rec, v_rec]
+    return {"workload": "vector BPs: BP2/BP4/BP6 (3 components) vs BP1/BP3/BP5, N=7, "
+                        "E=48x48x48, 100 fixed PCG iterations, rhs seeds 0,1,2",
+            "unit": "DOFs/s (components x n / s)", "records": rows}
+
+
+def manufactured_problem(N, grid, fp32):
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2004_06722_amd.bp as B
+    xi, _ = B.rule(N + 1, B.GLL)
+    mesh = synth.brick_mesh(*grid, N, xi, seed=0)
+    op = B.Operator(N, N + 1, B.GLL, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, mesh.boundary,
+                    fp32=fp32)
+    xyz = torch.from_numpy(mesh.global_coords()).cuda()
+    ue = (torch.sin(np.pi * xyz[:, 0]) * torch.sin(np.pi * xyz[:, 1])
+          * torch.sin(np.pi * xyz[:, 2])).contiguous()
+    b = op.apply(B.MASS, (3 * np.pi ** 2 * ue).contiguous(), masked=False)
+    b = b * torch.from_numpy(1.0 - mesh.boundary.astype(np.float64)).cuda()
+    return op, b, ue, mesh.nglobal
+
+
+def workload_mixed(args):
+    """FP32-inner defect correction against FP64 PCG, both to 1e-10."""
+    import torch
+    grid = synth_grid(18)
+    op, b, ue, nu = manufactured_problem(7, grid, fp32=True)
+    op.pcg_solve(b, maxit=5, fixed_iters=True)          # warm-up
+    op.pcg_solve_mixed(b, outer_rtol=1e-2, inner_rtol=1e-1, max_inner=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x64, st64 = op.pcg_solve(b, rtol=1e-10, maxit=100000)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xm, stm = op.pcg_solve_mixed(b, outer_rtol=1e-10, inner_rtol=1e-5, max_outer=50,
+                                 max_inner=100000)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    rec = {"workload": "BP5 N=7 E=64x64x64 manufactured solution sin(pi x)sin(pi y)sin(pi z), "
+                       "rhs = M f; FP64 Jacobi-PCG vs FP32-inner (rtol 1e-5) FP64 defect "
+                       "correction, both to relative residual 1e-10",
+           "fp64": {"seconds": t64, "iters": st64["iters"], "rel_res": st64["rel_res"][0],
+                    "max_err_vs_exact": (x64 - ue).abs().max().item()},
+           "mixed": {"seconds": tm, "outer": stm["outer"], "inner_iters": stm["iters"],
+                     "rel_res": stm["rel_res"][0],
+                     "max_err_vs_exact": (xm - ue).abs().max().item()},
+           "speedup": t64 / tm,
+           "rel_diff_mixed_vs_fp64": ((xm - x64).norm() / x64.norm()).item()}
+    op.close()
+    return rec
+
+
+def synth_grid(k):
+    import synth
+    return synth.element_grid(k)
+
+
+def workload_adjoint(args):
+    """Variable-coefficient Poisson with 8 right-hand sides: forward, loss,
+    adjoint gradient, and a 32-direction central finite-difference check."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2004_06722_amd.bp as B
+    from paper_2004_06722_amd.autograd import mass_norm_loss, poisson_solve
+    N, grid, nc = 5, (32, 32, 32), 8
+    rtol, maxit = 1e-13, 20000
+    t0 = time.perf_counter()
+    xi, _ = B.rule(N + 1, B.GLL)
+    mesh = synth.brick_mesh(*grid, N, xi, seed=0)
+    op = B.Operator(N, N + 1, B.GLL, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, mesh.boundary,
+                    ncomp=nc)
+    kap = synth.kappa_log(mesh.node_xyz, 0)              # GLL: quadrature points = nodes
+    b = torch.from_numpy(np.ascontiguousarray(synth.rhs_uniform(
+        mesh.nglobal, 100, ncomp=nc, dirichlet=mesh.boundary).T)).cuda()
+    log(f"setup {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    ut, st = op.pcg_solve(b, rtol=rtol, maxit=maxit)      # kappa = 1 target
+    log(f"target solve: {st['iters']} iterations, converged {st['converged']}, "
+        f"rel.res {max(st['rel_res']):.2e}, {time.perf_counter() - t0:.1f} s")
+    k_t = torch.from_numpy(kap).cuda().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = poisson_solve(op, k_t, b, rtol=rtol, maxit=maxit)
+    L = mass_norm_loss(op, u, ut)
+    L.backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    log(f"forward + loss + adjoint gradient: {t_fb:.2f} s, loss {L.item():.6e}")
+    g = k_t.grad.cpu().numpy()
+    u0 = u.detach()
+
+    def loss_at(kk):
+        op.set_coeff(torch.from_numpy(kk).cuda())
+        us, st = op.pcg_solve(b, x=u0.clone(), rtol=1e-15, maxit=maxit)
+        d = us - ut
+        return 0.5 * torch.sum(d * op.apply(B.MASS, d, masked=False)).item(), st["iters"]
+
+    # Richardson-extrapolated central differences: D(h) = (L(k+h d) - L(k-h d)) / 2h,
+    # R = (4 D(h/2) - D(h)) / 3 has an O(h^4) truncation error, so h can be
+    # large enough that the rounding noise of L (solves to 1e-15) stays small.
+    h = 4e-3
+    worst, worst_scaled, fds = 0.0, 0.0, []
+    gnorm = float(np.linalg.norm(g))
+    t0 = time.perf_counter()
+    for j in range(args.fd_directions):
+        dlt = synth.fd_direction(kap.shape, 1000 + j)
+        D = []
+        for hh in (h, h / 2):
+            lp, i1 = loss_at(kap + hh * dlt)
+            lm, i2 = loss_at(kap - hh * dlt)
+            D.append((lp - lm) / (2 * hh))
+        fd = (4 * D[1] - D[0]) / 3
+        an = float(np.sum(g * dlt))
+        err = abs(fd - an) / abs(an)
+        scaled = abs(fd - an) / (gnorm * float(np.linalg.norm(dlt)))
+        worst, worst_scaled = max(worst, err), max(worst_scaled, scaled)
+        fds.append([an, fd, err])
+        log(f"FD direction {j}: adjoint {an:.12e} fd {fd:.12e} rel.err {err:.2e} "
+            f"({i1} iterations per solve, {time.perf_counter() - t0:.1f} s)")
+    t_fd = time.perf_counter() - t0
+    op.close()
+    return {"workload": "variable-kappa Poisson N=5 E=32x32x32 (n=4,096,000 per rhs), 8 rhs, "
+                        "kappa = exp(16-mode field), loss 1/2|u-u_t|_M^2, adjoint gradient, "
+                        f"{args.fd_directions} directions, Richardson-extrapolated central differences "
+                        "(h = 4e-3, 2e-3; warm-started solves to 1e-15)",
+            "loss": L.item(), "forward_backward_s": t_fb, "fd_seconds": t_fd,
+            "fd_max_rel_err": worst, "fd_max_err_scaled_by_norms": worst_scaled,
+            "fd_pass_1e-6_relative": worst <= 1e-6, "directions": fds}
+
+
+def workload_sweep13(args):
+    """BP1 and BP3 (GL q=N+2), N=1..8, E=2^k with n in [1e4, cap]: DOFs/s curves,
+    r_max and n_0.8 per (BP, N)."""
+    out = []
+    cap = 4e7
+    for bp in (1, 3):
+        for N in range(1, 9):
+            pts = []
+            for k in range(0, 30):
+                E = 2 ** k
+                n = N ** 3 * E
+                if n < 1e4:
+                    continue
+                if n > cap or E > 2 ** 24:
+                    break
+                rec = run_fixed(bp, N, synth_grid(k), 1, steps=100, warmup=5)
+                pts.append((n, rec["DOFs_per_s"], rec["apply_frac_hbm"], rec["iter_alg_frac_hbm"]))
+            rmax, n08, t08 = n08_from_sweep([(a, b) for a, b, _, _ in pts])
+            best = max(pts, key=lambda t: t[1])
+            log(f"BP{bp} N={N}: r_max {rmax:.3e} n_0.8 {n08:.3e} (apply {best[2]:.2f}, iter {best[3]:.2f} of HBM)")
+            out.append({"bp": bp, "N": N, "r_max": rmax, "n_0.8": n08, "t_0.8_s": t08,
+                        "apply_frac_hbm_at_rmax": best[2], "iter_frac_hbm_at_rmax": best[3],
+                        "points": [[a, b] for a, b, _, _ in pts]})
+    return {"workload": f"BP1/BP3 sweep, N=1..8, E=2^k <= 2^24 with 1e4 <= N^3 E <= {cap:.0e}, "
+                        "100 fixed PCG iterations each, rhs uniform seed 0", "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,9 +366,20 @@ def main():
     ap.add_argument("--sweep-k", default="5:17", help="sweep E = 2^k for k in lo:hi")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run only the counter calibration copy")
+    ap.add_argument("--fd-directions", type=int, default=32, help="adjoint workload: FD directions")
+    ap.add_argument("--workload", default="bp5",
+                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13"],
+                    help="bp5: the headline line; the others print their own record")
     args = ap.parse_args()
     if args.calib_copy:
         calib_copy()
+        return
+    if args.workload != "bp5":
+        import torch
+        torch.cuda.set_device(0)
+        fn = {"vector": workload_vector, "mixed": workload_mixed, "adjoint": workload_adjoint,
+              "sweep13": workload_sweep13}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "

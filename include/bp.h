@@ -13,8 +13,8 @@
  *     for BP1-BP4, GLL q = p+1 for BP5-BP6).
  *   - Element-local node (i, j, k) has local id l = i + p1*(j + p1*k), i the
  *     fastest index (eq. (xijk)/(uijk)); quadrature point (a, b, c) likewise.
- *   - Global vectors are device arrays [nglobal][ncomp] (components
- *     interleaved, component fastest), FP64 unless stated.
+ *   - Global vectors are device arrays [ncomp][nglobal] (component-major:
+ *     component c of node g at c * nglobal + g), FP64 unless stated.
  *   - Every call that takes a `stream` enqueues its device work on that HIP
  *     stream (hipStream_t passed as void*, NULL = the null stream) and returns
  *     without waiting, unless stated otherwise.
@@ -112,7 +112,7 @@ int bp_set_coeff(bp_op op, const double *kappa_q, void *stream);
  * Section 4 (w = Q^T A_L Q u), section 5 eq. (bk5x) / eq. (mass); with
  * BP_MASKED, w = mask * A (mask * u) as the Dirichlet restriction of
  * Appendix A1 (Nek5000 ax).
- *   prec = BP_FP64: u, w are double [nglobal][ncomp].
+ *   prec = BP_FP64: u, w are double [ncomp][nglobal].
  *   prec = BP_FP32: u, w are float; requires BP_SETUP_FP32.
  *   w is overwritten (it must not alias u).
  */
@@ -146,7 +146,7 @@ typedef struct {
  * BP_STIFF solves the masked stiffness system (BP3-BP6; Dirichlet nodes stay
  * 0); BP_MASS solves the unmasked mass system (BP1, BP2) -- if the operator
  * was built with Dirichlet nodes the mass system is masked too.
- *   b: device double [nglobal][ncomp]; x: device double, in: x0, out: solution.
+ *   b: device double [ncomp][nglobal]; x: device double, in: x0, out: solution.
  *   fixed_iters != 0: exactly maxit iterations, no convergence test (the
  *     timing mode of section 2); otherwise stop at the first iteration with
  *     max_c ||r_c|| / ||b_c|| <= rtol, or at maxit (converged = 0, not an error).
@@ -174,7 +174,7 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
  * bp_grad_kappa -- g_q = - sum_c (D lam_c)_q^T G_q (D u_c)_q per element and
  * quadrature point: the derivative of lam^T A(kappa) u with respect to the
  * coefficient (section 4 eq. (ip1) with mu = kappa; section 5 eq. (bk5x)),
- * summed over the ncomp components. lam, u: device double [nglobal][ncomp]
+ * summed over the ncomp components. lam, u: device double [ncomp][nglobal]
  * (masked on Dirichlet nodes); g: device double [nelem][q^3], overwritten.
  */
 int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,

@@ -1,7 +1,8 @@
 """Python binding of the bake-off library: argument marshalling only.
 
 Every computation runs in libbp.so's HIP kernels; torch supplies device
-memory (tensors) and the current HIP stream.
+memory (tensors) and the current HIP stream. Vectors with several components
+are component-major tensors [ncomp, nglobal].
 """
 from __future__ import annotations
 
@@ -104,7 +105,8 @@ class Operator:
         return t
 
     def new_vector(self, dtype=torch.float64) -> torch.Tensor:
-        shape = (self.nglobal,) if self.ncomp == 1 else (self.nglobal, self.ncomp)
+        """Zero vector; component-major [ncomp, nglobal] when ncomp > 1."""
+        shape = (self.nglobal,) if self.ncomp == 1 else (self.ncomp, self.nglobal)
         return torch.zeros(shape, dtype=dtype, device=self.device)
 
     def apply(self, which: int, u: torch.Tensor, out: torch.Tensor | None = None,

@@ -352,8 +352,9 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRY(dmalloc(&op->w, nv));
   TRY(dmalloc(&op->tmp, std::max<int64_t>(nv, nglobal)));
   // partial sums of the largest grid, followed by the stage-1 rows
-  op->part_len = std::max<int64_t>(apply_blocks(op) * ncomp, vec_blocks(nglobal) * 3 * ncomp) +
-                 kStage2Rows * 3 * ncomp;
+  op->part_len =
+      std::max<int64_t>(apply_blocks(op) * ncomp, vec_blocks(nglobal) * 3 * ncomp) +
+      kStage2Rows * 3 * ncomp;
   TRY(dmalloc(&op->part, op->part_len));
   TRY(dmalloc(&op->sc, 1));
   TRYHIP(hipHostMalloc((void **)&op->sc_host, sizeof(DevScalars), hipHostMallocDefault));

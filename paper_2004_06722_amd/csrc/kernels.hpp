@@ -81,7 +81,10 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 
 // ---------------------------------------------------------------------------
 // BK5/BK6: stiffness with collocated GLL quadrature (J^ = I, q = p1).
-// NC components share every load of G and of the gather map.
+// One component per launch: u and w point at component c0 (vectors are
+// component-major, [ncomp][nglobal]); ncomp and c0 place the energy partial. Keeping
+// the G column in registers across several components doubles the register
+// footprint and halves occupancy, which costs more than re-reading G.
 //
 // The kernel is bound by HBM latency more than by arithmetic, so it is laid
 // out to need few dependent round trips: each lane requests its whole column
@@ -95,11 +98,12 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
 // accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
 // ---------------------------------------------------------------------------
-template <int P1, int NC, typename T>
+template <int P1, typename T>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *Dg,
     const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0, int masked,
     double *__restrict__ part, const int *__restrict__ done) {
+  constexpr int NC = 1;  // one component per launch; G is re-read per component
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
   if (done && *done) return;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int k = 0; k < P1; ++k) ru[c][k] = u[(int64_t)gk[k] * ncomp + c0 + c] * mk[k];
+    for (int k = 0; k < P1; ++k) ru[c][k] = u[gk[k]] * mk[k];
   for (int x = t; x < PP; x += PL::THREADS) {
     sD[x / P1][x % P1] = Dg[x];
     sDt[x % P1][x / P1] = Dg[x];
@@ -183,7 +187,9 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
       const T vr = g[0][k] * ur + g[1][k] * us + g[2][k] * ut;
       const T vs = g[1][k] * ur + g[3][k] * us + g[4][k] * ut;
       const T vt = g[2][k] * ur + g[4][k] * us + g[5][k] * ut;
-      en[c] += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
+      // idle lanes of a partly used wave read another element's tile: no energy
+      if (act)
+        en[c] += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
       rt[c][k] = vt;
       if (act) {
         sr[slot][c][k][j][i] = vr;
@@ -205,7 +211,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
         acc += sDt[i][m] * sr[slot][c][k][j][m];
         acc += sDt[j][m] * ss[slot][c][k][m][i];
       }
-      if (mk[k] != T(0)) atomic_add(w + (int64_t)gk[k] * ncomp + c0 + c, acc);
+      if (mk[k] != T(0)) atomic_add(w + gk[k], acc);
     }
   }
   if (part) block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0, 1);
@@ -218,7 +224,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 template <int P1, typename T>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Bt,
-    const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0, int ncg, int masked,
+    const T *__restrict__ u, T *__restrict__ w, int64_t cstride, int ncomp, int masked,
     double *__restrict__ part, const int *__restrict__ done) {
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1;
@@ -237,18 +243,18 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
     gk[k] = decode_index(v, live, masked);
     b[k] = live ? Bt[e * N3 + k * P1 * P1 + ij] : T(0);
   }
-  for (int cc = 0; cc < ncg; ++cc) {
+  for (int cc = 0; cc < ncomp; ++cc) {
     double en[1] = {0.0};
 #pragma unroll
     for (int k = 0; k < P1; ++k) {
       if (gk[k] < 0) continue;
-      const int64_t o = (int64_t)gk[k] * ncomp + c0 + cc;
+      const int64_t o = gk[k] + cc * cstride;
       const T uv = u[o];
       const T wv = b[k] * uv;
       en[0] += (double)uv * (double)wv;
       atomic_add(w + o, wv);
     }
-    if (part) block_sum_store<1, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0 + cc, 1);
+    if (part) block_sum_store<1, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + cc, 1);
     __syncthreads();
   }
 }
@@ -257,154 +263,194 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
 // BK1-BK4: Gauss-Legendre quadrature (q > p1). Interpolate to the quadrature
 // points first (u~ = J u), differentiate there with the q x q matrix D~
 // (section 5, eq. (gradr2)-(gradt2)), apply G (stiffness) or B~ (mass), and
-// return with the transposed operations. Thread plane (a, b) over q x q.
+// return with the transposed operations. Every stage is one 1D contraction
+// between padded q x q x q LDS tiles, so a lane holds only one line of values
+// at a time and registers stay free for the G column, which (with the gather
+// map) is requested at entry. Thread (a, b) of the q x q plane owns the
+// quadrature column (a, b, .); lanes with a, b < p1 also own node column
+// (a, b, .). The local energy is accumulated at the quadrature points.
 // ---------------------------------------------------------------------------
 template <int P1, int Q, typename T, bool STIFF>
 __global__ __launch_bounds__((Plane<P1, Q>::THREADS)) void k_op_interp(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
-    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp,
-    int c0, int ncg, int masked, double *__restrict__ part, const int *__restrict__ done) {
+    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int64_t cstride,
+    int ncomp, int masked, double *__restrict__ part, const int *__restrict__ done) {
   using PL = Plane<P1, Q>;
-  constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QP = Q + 1;
+  constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QQ = Q * Q, QP = Q + 1;
+  constexpr int NG = STIFF ? 6 : 1;
+  constexpr int NT = STIFF ? 4 : 3;  // LDS tiles
   static_assert(Q > P1, "interpolating kernel expects q > p1");
   if (done && *done) return;
-  __shared__ T sJ[Q][P1];
-  __shared__ T sDq[Q][Q];
-  __shared__ T s1[PL::EPB][Q][Q][QP];
-  __shared__ T s2[PL::EPB][Q][Q][QP];
-  __shared__ T s3[PL::EPB][Q][Q][QP];
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
   const int slot = act ? t / PL::N : 0;
   const int ab = t % PL::N;
   const int a = ab % Q, b = ab / Q;
   const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
+  if (PL::EPB == 1 && e >= nelem) return;  // uniform over the work-group
   const bool live = act && e < nelem;
+  const int64_t ec = live ? e : nelem - 1;
   const bool own = live && a < P1 && b < P1;  // owns node column (i=a, j=b)
-  for (int x = t; x < Q * P1; x += PL::THREADS) sJ[x / P1][x % P1] = basis[x];
-  for (int x = t; x < Q * Q; x += PL::THREADS) sDq[x / Q][x % Q] = basis[2 * Q * P1 + x];
+
+  __shared__ T sJ[Q][P1 + 1];   // sJ[a][i]  = J^[a][i]
+  __shared__ T sJt[P1][QP];     // sJt[i][a] = J^[a][i]
+  __shared__ T sDq[Q][QP];      // sDq[a][m] = D~[a][m]
+  __shared__ T sDqt[Q][QP];     // sDqt[m][a] = D~[a][m]
+  __shared__ T tile[NT][PL::EPB][Q][Q][QP];
+
+  // one round trip: gather map (node columns) and G / B~ (quadrature columns)
   int gk[P1];
+  T mk[P1];
+  const int ia = a < P1 ? a : 0, jb = b < P1 ? b : 0;
+#pragma unroll
+  for (int k = 0; k < P1; ++k) gk[k] = idx[ec * N3 + ia + P1 * (jb + P1 * k)];
+  T g[NG][Q];
+  const T *Ge = Gm + ec * NG * NQ + ab;
+#pragma unroll
+  for (int c = 0; c < Q; ++c)
+#pragma unroll
+    for (int n = 0; n < NG; ++n) g[n][c] = __builtin_nontemporal_load(Ge + n * NQ + c * QQ);
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
-    const int v = own ? idx[e * N3 + a + P1 * (b + P1 * k)] : -1;
-    gk[k] = decode_index(v, own, masked);
+    const int v = gk[k];
+    mk[k] = (own && (v >= 0 || !masked)) ? T(1) : T(0);
+    gk[k] = v >= 0 ? v : -1 - v;
   }
-  const T *Ge = Gm + (live ? e : 0) * (STIFF ? 6 : 1) * NQ + ab;
+  for (int x = t; x < Q * P1; x += PL::THREADS) {
+    const T v = basis[x];
+    sJ[x / P1][x % P1] = v;
+    sJt[x % P1][x / P1] = v;
+  }
+  for (int x = t; x < QQ; x += PL::THREADS) {
+    const T v = basis[2 * Q * P1 + x];
+    sDq[x / Q][x % Q] = v;
+    sDqt[x % Q][x / Q] = v;
+  }
+  T(&A)[Q][Q][QP] = tile[0][slot];
+  T(&B)[Q][Q][QP] = tile[1][slot];
+  T(&C)[Q][Q][QP] = tile[2][slot];
 
-  for (int cc = 0; cc < ncg; ++cc) {
-    const int comp = c0 + cc;
-    T ru[P1];
+  for (int comp = 0; comp < ncomp; ++comp) {
+    // gather: A[k][j][i] = u
 #pragma unroll
     for (int k = 0; k < P1; ++k) {
-      ru[k] = gk[k] >= 0 ? u[(int64_t)gk[k] * ncomp + comp] : T(0);
-      if (act && a < P1 && b < P1) s1[slot][k][b][a] = ru[k];
+      const T val = u[gk[k] + comp * cstride] * mk[k];
+      if (act && a < P1 && b < P1) A[k][b][a] = val;
     }
     __syncthreads();
-    // interpolate along r: s2[k][j][a] = sum_i J[a][i] u[k][j][i]
+    // interpolate along r: B[k][j][a] = sum_i J[a][i] A[k][j][i]   (b plays j)
     if (act && b < P1)
 #pragma unroll
       for (int k = 0; k < P1; ++k) {
         T s = 0;
 #pragma unroll
-        for (int m = 0; m < P1; ++m) s += sJ[a][m] * s1[slot][k][b][m];
-        s2[slot][k][b][a] = s;
+        for (int m = 0; m < P1; ++m) s += sJ[a][m] * A[k][b][m];
+        B[k][b][a] = s;
       }
     __syncthreads();
-    // along s: s3[k][b][a] = sum_j J[b][j] s2[k][j][a]
+    // along s: A[k][b][a] = sum_j J[b][j] B[k][j][a]
     if (act)
 #pragma unroll
       for (int k = 0; k < P1; ++k) {
         T s = 0;
 #pragma unroll
-        for (int m = 0; m < P1; ++m) s += sJ[b][m] * s2[slot][k][m][a];
-        s3[slot][k][b][a] = s;
+        for (int m = 0; m < P1; ++m) s += sJ[b][m] * B[k][m][a];
+        A[k][b][a] = s;
       }
     __syncthreads();
-    // along t: uq[c] in registers
-    T uq[Q];
+    // along t: B[c][b][a] = sum_k J[c][k] A[k][b][a]
+    double en = 0.0;
+    if (act) {
+      T col[P1];
 #pragma unroll
-    for (int c = 0; c < Q; ++c) {
-      T s = 0;
+      for (int k = 0; k < P1; ++k) col[k] = A[k][b][a];
 #pragma unroll
-      for (int m = 0; m < P1; ++m) s += sJ[c][m] * s3[slot][m][b][a];
-      uq[c] = s;
+      for (int c = 0; c < Q; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < P1; ++k) s += sJ[c][k] * col[k];
+        if constexpr (STIFF) {
+          B[c][b][a] = s;
+        } else {
+          const T v = g[0][c] * s;  // B~ at the point
+          en += (double)s * (double)v;
+          B[c][b][a] = v;
+        }
+      }
     }
-    T tv[Q];
+    __syncthreads();
     if constexpr (STIFF) {
+      T(&Dt)[Q][Q][QP] = tile[3][slot];
+      // derivatives at the quadrature points, G, into A (r), C (s), Dt (t)
       if (act)
 #pragma unroll
-        for (int c = 0; c < Q; ++c) s1[slot][c][b][a] = uq[c];
+        for (int c = 0; c < Q; ++c) {
+          T ur = 0, us = 0, ut = 0;
+#pragma unroll
+          for (int m = 0; m < Q; ++m) {
+            ur += sDq[a][m] * B[c][b][m];
+            us += sDq[b][m] * B[c][m][a];
+            ut += sDq[c][m] * B[m][b][a];
+          }
+          const T vr = g[0][c] * ur + g[1][c] * us + g[2][c] * ut;
+          const T vs = g[1][c] * ur + g[3][c] * us + g[4][c] * ut;
+          const T vt = g[2][c] * ur + g[4][c] * us + g[5][c] * ut;
+          en += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
+          A[c][b][a] = vr;
+          C[c][b][a] = vs;
+          Dt[c][b][a] = vt;
+        }
       __syncthreads();
-      T rv[Q];
+      // transposed derivatives into B
+      if (act)
 #pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T ur = 0, us = 0, ut = 0;
+        for (int c = 0; c < Q; ++c) {
+          T s = 0;
 #pragma unroll
-        for (int m = 0; m < Q; ++m) {
-          ur += sDq[a][m] * s1[slot][c][b][m];
-          us += sDq[b][m] * s1[slot][c][m][a];
-          ut += sDq[c][m] * uq[m];
+          for (int m = 0; m < Q; ++m) {
+            s += sDqt[a][m] * A[c][b][m];
+            s += sDqt[b][m] * C[c][m][a];
+            s += sDqt[c][m] * Dt[m][b][a];
+          }
+          B[c][b][a] = s;
         }
-        T g[6];
-#pragma unroll
-        for (int n = 0; n < 6; ++n) g[n] = live ? Ge[n * NQ + c * Q * Q] : T(0);
-        const T vr = g[0] * ur + g[1] * us + g[2] * ut;
-        const T vs = g[1] * ur + g[3] * us + g[4] * ut;
-        rv[c] = g[2] * ur + g[4] * us + g[5] * ut;
-        if (act) {
-          s2[slot][c][b][a] = vr;
-          s3[slot][c][b][a] = vs;
-        }
-      }
       __syncthreads();
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T s = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) {
-          s += sDq[m][c] * rv[m];
-          s += sDq[m][a] * s2[slot][c][b][m];
-          s += sDq[m][b] * s3[slot][c][m][a];
-        }
-        tv[c] = s;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < Q; ++c) tv[c] = (live ? Ge[c * Q * Q] : T(0)) * uq[c];
     }
-    __syncthreads();
-    // transposed interpolation along t: s1[k][b][a] = sum_c J[c][k] tv[c]
-    if (act)
+    // transposed interpolation along t: A[k][b][a] = sum_c J[c][k] B[c][b][a]
+    if (act) {
+      T col[Q];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) col[c] = B[c][b][a];
 #pragma unroll
       for (int k = 0; k < P1; ++k) {
         T s = 0;
 #pragma unroll
-        for (int c = 0; c < Q; ++c) s += sJ[c][k] * tv[c];
-        s1[slot][k][b][a] = s;
+        for (int c = 0; c < Q; ++c) s += sJt[k][c] * col[c];
+        A[k][b][a] = s;
       }
+    }
     __syncthreads();
-    // along s: s2[k][j][a] = sum_b J[b][j] s1[k][b][a]
+    // along s: C[k][j][a] = sum_b J[b][j] A[k][b][a]
     if (act && b < P1)
 #pragma unroll
       for (int k = 0; k < P1; ++k) {
         T s = 0;
 #pragma unroll
-        for (int m = 0; m < Q; ++m) s += sJ[m][b] * s1[slot][k][m][a];
-        s2[slot][k][b][a] = s;
+        for (int m = 0; m < Q; ++m) s += sJt[b][m] * A[k][m][a];
+        C[k][b][a] = s;
       }
     __syncthreads();
-    // along r, energy, scatter
-    double en[1] = {0.0};
+    // along r and scatter: w(i,j,k) = sum_a J[a][i] C[k][j][a]
     if (act && a < P1 && b < P1)
 #pragma unroll
       for (int k = 0; k < P1; ++k) {
         T s = 0;
 #pragma unroll
-        for (int m = 0; m < Q; ++m) s += sJ[m][a] * s2[slot][k][b][m];
-        en[0] += (double)ru[k] * (double)s;
-        if (gk[k] >= 0) atomic_add(w + (int64_t)gk[k] * ncomp + comp, s);
+        for (int m = 0; m < Q; ++m) s += sJt[a][m] * C[k][b][m];
+        if (mk[k] != T(0)) atomic_add(w + gk[k] + comp * cstride, s);
       }
-    if (part) block_sum_store<1, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + comp, 1);
+    double enb[1] = {en};
+    if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + comp, 1);
     __syncthreads();
   }
 }
@@ -496,7 +542,7 @@ template <int P1>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const double *__restrict__ G,
     const double *__restrict__ basis, const double *__restrict__ lam,
-    const double *__restrict__ u, double *__restrict__ gout, int ncomp) {
+    const double *__restrict__ u, double *__restrict__ gout, int64_t cstride, int ncomp) {
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PAD = P1 + 1;
   __shared__ double sD[P1][P1];
@@ -523,8 +569,8 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
     double rl[P1], rv[P1];
 #pragma unroll
     for (int k = 0; k < P1; ++k) {
-      rl[k] = gk[k] >= 0 ? lam[(int64_t)gk[k] * ncomp + c] : 0.0;
-      rv[k] = gk[k] >= 0 ? u[(int64_t)gk[k] * ncomp + c] : 0.0;
+      rl[k] = gk[k] >= 0 ? lam[gk[k] + c * cstride] : 0.0;
+      rv[k] = gk[k] >= 0 ? u[gk[k] + c * cstride] : 0.0;
       if (act) {
         sl[slot][k][j][i] = rl[k];
         su[slot][k][j][i] = rv[k];

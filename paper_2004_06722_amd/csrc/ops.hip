@@ -23,21 +23,11 @@ template <int P1, typename T>
 int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *u, T *w, int masked,
                  double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
-  const int64_t nb = apply_blocks(op);
   const T *Dg = basis + P1 * P1;  // D^ follows J^ (both p1 x p1 here)
-  for (int c0 = 0; c0 < op->ncomp;) {
-    const int g = op->ncomp - c0 >= 3 ? 3 : op->ncomp - c0;
-    if (g == 3)
-      hipLaunchKernelGGL((k_stiff_colloc<P1, 3, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
-                         op->idx, G, Dg, u, w, op->ncomp, c0, masked, part, done);
-    else if (g == 2)
-      hipLaunchKernelGGL((k_stiff_colloc<P1, 2, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
-                         op->idx, G, Dg, u, w, op->ncomp, c0, masked, part, done);
-    else
-      hipLaunchKernelGGL((k_stiff_colloc<P1, 1, T>), dim3(nb), dim3(PL::THREADS), 0, s, op->nelem,
-                         op->idx, G, Dg, u, w, op->ncomp, c0, masked, part, done);
-    c0 += g;
-  }
+  for (int c = 0; c < op->ncomp; ++c)
+    hipLaunchKernelGGL((k_stiff_colloc<P1, T>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
+                       op->nelem, op->idx, G, Dg, u + c * op->nglobal, w + c * op->nglobal,
+                       op->ncomp, c, masked, part, done);
   return BP_OK;
 }
 
@@ -46,7 +36,7 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
                 const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
   hipLaunchKernelGGL((k_mass_colloc<P1, T>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
-                     op->nelem, op->idx, Bt, u, w, op->ncomp, 0, op->ncomp, masked, part, done);
+                     op->nelem, op->idx, Bt, u, w, op->nglobal, op->ncomp, masked, part, done);
   return BP_OK;
 }
 
@@ -55,7 +45,7 @@ int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int
            double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, Q>;
   hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(apply_blocks(op)), dim3(PL::THREADS),
-                     0, s, op->nelem, op->idx, Gm, basis, u, w, op->ncomp, 0, op->ncomp, masked,
+                     0, s, op->nelem, op->idx, Gm, basis, u, w, op->nglobal, op->ncomp, masked,
                      part, done);
   return BP_OK;
 }
@@ -91,7 +81,7 @@ void grad_colloc(const bp_op_s *op, const double *lam, const double *u, double *
                  hipStream_t s) {
   using PL = Plane<P1, P1>;
   hipLaunchKernelGGL((k_grad_kappa_colloc<P1>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
-                     op->nelem, op->idx, op->G, op->basis_d, lam, u, g, op->ncomp);
+                     op->nelem, op->idx, op->G, op->basis_d, lam, u, g, op->nglobal, op->ncomp);
 }
 
 }  // namespace

@@ -15,32 +15,6 @@ namespace {
 
 constexpr int kFinThreads = 1024;
 
-// Block sum of NC doubles per thread into part[blk * width + off + c].
-template <int NC>
-__device__ __forceinline__ void block_partials(double (&v)[NC], double *part, int width, int off) {
-  constexpr int NW = kVecThreads / 64;
-  __shared__ double red[NW][NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    double x = v[c];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    v[c] = x;
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) red[wid][c] = v[c];
-  __syncthreads();
-  if (threadIdx.x < NC) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) s += red[k][threadIdx.x];
-    part[(int64_t)blockIdx.x * width + off + threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
 // Fixed-order sum of `width` columns over nb rows: res[col] (shared).
 __device__ void reduce_columns(const double *__restrict__ part, int64_t nb, int width,
                                double *res) {
@@ -114,39 +88,55 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
     x[i] = v;
 }
 
+// The CG kernels run one node per thread over a 2D grid: blockIdx.y is the
+// component (vectors are component-major, [nc][n]). A work-group writes its
+// partial sum into row blockIdx.x, column (quantity * nc + component), of a
+// [gridDim.x][q * nc] table; every entry is written by exactly one group.
+__device__ __forceinline__ void block_partial1(double v, double *part, int width, int col) {
+  constexpr int NW = kVecThreads / 64;
+  __shared__ double red[NW];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[k];
+    part[(int64_t)blockIdx.x * width + col] = s;
+  }
+  __syncthreads();
+}
+
 // r = b - w (w holds A x0), w = 0, p = z = dinv r; partials r.z, r.r, b.b.
 // Entries of b on Dirichlet nodes are treated as zero.
-template <int NC, typename T>
+template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_cg_init(int64_t n, const T *__restrict__ b,
                                                          T *__restrict__ r, T *__restrict__ w,
                                                          T *__restrict__ p,
                                                          const T *__restrict__ dinv,
                                                          double *__restrict__ part) {
-  double rz[NC], rr[NC], bb[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) rz[c] = rr[c] = bb[c] = 0.0;
+  const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double rz = 0.0, rr = 0.0, bb = 0.0;
   if (v < n) {
+    const int64_t f = comp * n + v;
     const T di = dinv[v];
     // dinv = 0 exactly on Dirichlet nodes: b is read as 0 there
     const bool free = di != T(0);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int64_t o = v * NC + c;
-      const T bv = free ? b[o] : T(0);
-      const T rv = free ? bv - w[o] : T(0);
-      const T z = di * rv;
-      r[o] = rv;
-      p[o] = z;
-      w[o] = T(0);
-      rz[c] += (double)rv * (double)z;
-      rr[c] += (double)rv * (double)rv;
-      bb[c] += (double)bv * (double)bv;
-    }
+    const T bv = free ? b[f] : T(0);
+    const T rv = free ? bv - w[f] : T(0);
+    const T z = di * rv;
+    r[f] = rv;
+    p[f] = z;
+    w[f] = T(0);
+    rz = (double)rv * (double)z;
+    rr = (double)rv * (double)rv;
+    bb = (double)bv * (double)bv;
   }
-  block_partials<NC>(rz, part, 3 * NC, 0);
-  block_partials<NC>(rr, part, 3 * NC, NC);
-  block_partials<NC>(bb, part, 3 * NC, 2 * NC);
+  block_partial1(rz, part, 3 * nc, comp);
+  block_partial1(rr, part, 3 * nc, nc + comp);
+  block_partial1(bb, part, 3 * nc, 2 * nc + comp);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restrict__ part,
@@ -185,34 +175,27 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
 }
 
 // x += alpha p; r -= alpha w; w = 0; partials r.z (z = dinv r) and r.r.
-template <int NC, typename T>
+template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update_xr(
     int64_t n, T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r, T *__restrict__ w,
     const T *__restrict__ dinv, double *__restrict__ part, const DevScalars *__restrict__ sc) {
   if (sc->done) return;
-  T al[NC];
-  double rz[NC], rr[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    al[c] = (T)sc->alpha[c];
-    rz[c] = rr[c] = 0.0;
-  }
+  const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
   if (v < n) {
+    const int64_t f = comp * n + v;
+    const T al = (T)sc->alpha[comp];
     const T di = dinv[v];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int64_t o = v * NC + c;
-      x[o] += al[c] * p[o];
-      const T rv = r[o] - al[c] * w[o];
-      r[o] = rv;
-      w[o] = T(0);
-      rz[c] += (double)rv * (double)(di * rv);
-      rr[c] += (double)rv * (double)rv;
-    }
+    x[f] += al * p[f];
+    const T rv = r[f] - al * w[f];
+    r[f] = rv;
+    w[f] = T(0);
+    rz = (double)rv * (double)(di * rv);
+    rr = (double)rv * (double)rv;
   }
-  block_partials<NC>(rz, part, 2 * NC, 0);
-  block_partials<NC>(rr, part, 2 * NC, NC);
+  block_partial1(rz, part, 2 * nc, comp);
+  block_partial1(rr, part, 2 * nc, nc + comp);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restrict__ part,
@@ -234,49 +217,37 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restri
 }
 
 // p = dinv r + beta p
-template <int NC, typename T>
+template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update_p(int64_t n, T *__restrict__ p,
                                                              const T *__restrict__ r,
                                                              const T *__restrict__ dinv,
                                                              const DevScalars *__restrict__ sc) {
   if (sc->done) return;
-  T be[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) be[c] = (T)sc->beta[c];
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   if (v < n) {
-    const T di = dinv[v];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int64_t o = v * NC + c;
-      p[o] = di * r[o] + be[c] * p[o];
-    }
+    const int64_t f = blockIdx.y * n + v;
+    p[f] = dinv[v] * r[f] + (T)sc->beta[blockIdx.y] * p[f];
   }
 }
 
 // r = b - w, w = 0; partials r.r and b.b
-template <int NC>
 __global__ __launch_bounds__(kVecThreads) void k_dc_residual(int64_t n, const double *__restrict__ b,
                                                              double *__restrict__ r,
                                                              double *__restrict__ w,
                                                              double *__restrict__ part) {
-  double rr[NC], bb[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) rr[c] = bb[c] = 0.0;
+  const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double rr = 0.0, bb = 0.0;
   if (v < n) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int64_t o = v * NC + c;
-      const double rv = b[o] - w[o];
-      r[o] = rv;
-      w[o] = 0.0;
-      rr[c] += rv * rv;
-      bb[c] += b[o] * b[o];
-    }
+    const int64_t f = comp * n + v;
+    const double rv = b[f] - w[f];
+    r[f] = rv;
+    w[f] = 0.0;
+    rr = rv * rv;
+    bb = b[f] * b[f];
   }
-  block_partials<NC>(rr, part, 2 * NC, 0);
-  block_partials<NC>(bb, part, 2 * NC, NC);
+  block_partial1(rr, part, 2 * nc, comp);
+  block_partial1(bb, part, 2 * nc, nc + comp);
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_norms(const double *__restrict__ part,
@@ -380,26 +351,12 @@ void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk3
                      G, kappa, Gk, Gk32, nelem, nq);
 }
 
-#define BP_NC_SWITCH(nc, MACRO) \
-  switch (nc) {                 \
-    case 1: MACRO(1); break;    \
-    case 2: MACRO(2); break;    \
-    case 3: MACRO(3); break;    \
-    case 4: MACRO(4); break;    \
-    case 5: MACRO(5); break;    \
-    case 6: MACRO(6); break;    \
-    case 7: MACRO(7); break;    \
-    default: MACRO(8); break;   \
-  }
-
 template <typename T>
 void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, double *part,
              DevScalars *sc, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
-#define L(NC) \
-  hipLaunchKernelGGL((k_cg_init<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, b, r, w, p, dinv, part)
-  BP_NC_SWITCH(nc, L)
-#undef L
+  hipLaunchKernelGGL((k_cg_init<T>), dim3(nb, nc), dim3(kVecThreads), 0, s, n, b, r, w, p, dinv,
+                     part);
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, 3 * nc, part + nb * 3 * nc, &rows, s);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
@@ -414,12 +371,8 @@ void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStr
 template <typename T>
 void cg_update_xr(int nc, int64_t n, T *x, const T *p, T *r, T *w, const T *dinv, double *part,
                   DevScalars *sc, hipStream_t s) {
-  const int64_t nb = vec_blocks(n);
-#define L(NC)                                                                                  \
-  hipLaunchKernelGGL((k_cg_update_xr<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, x, p, r, w, \
-                     dinv, part, sc)
-  BP_NC_SWITCH(nc, L)
-#undef L
+  hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x,
+                     p, r, w, dinv, part, sc);
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s) {
@@ -432,20 +385,14 @@ void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStre
 template <typename T>
 void cg_update_p(int nc, int64_t n, T *p, const T *r, const T *dinv, DevScalars *sc,
                  hipStream_t s) {
-  const int64_t nb = vec_blocks(n);
-#define L(NC) \
-  hipLaunchKernelGGL((k_cg_update_p<NC, T>), dim3(nb), dim3(kVecThreads), 0, s, n, p, r, dinv, sc)
-  BP_NC_SWITCH(nc, L)
-#undef L
+  hipLaunchKernelGGL((k_cg_update_p<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, p,
+                     r, dinv, sc);
 }
 
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,
                  DevScalars *sc, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
-#define L(NC) \
-  hipLaunchKernelGGL((k_dc_residual<NC>), dim3(nb), dim3(kVecThreads), 0, s, n, b, r, w, part)
-  BP_NC_SWITCH(nc, L)
-#undef L
+  hipLaunchKernelGGL(k_dc_residual, dim3(nb, nc), dim3(kVecThreads), 0, s, n, b, r, w, part);
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, 2 * nc, part + nb * 2 * nc, &rows, s);
   hipLaunchKernelGGL(k_fin_norms, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);

@@ -32,16 +32,17 @@ def test_loss_and_gradients_match_oracle():
     from paper_2004_06722_amd.autograd import mass_norm_loss, poisson_solve
     c, kap, b, ut, disc_k = setup_case()
     try:
+        # device vectors are component-major [ncomp, n]; the oracle's are [n, ncomp]
         k_t = torch.tensor(kap, device="cuda", requires_grad=True)
-        b_t = torch.tensor(b, device="cuda", requires_grad=True)
+        b_t = torch.tensor(b.T.copy(), device="cuda", requires_grad=True)
         u = poisson_solve(c.op, k_t, b_t, rtol=1e-14)
-        L = mass_norm_loss(c.op, u, torch.tensor(ut, device="cuda"))
+        L = mass_norm_loss(c.op, u, torch.tensor(ut.T.copy(), device="cuda"))
         L.backward()
         Lo, go, lam_o, uo = adjoint.loss_and_grad(disc_k, b, ut, rtol=1e-14)
         assert abs(L.item() - Lo) <= SOLVE_TOL * abs(Lo)
-        assert rel(u.detach().cpu().numpy(), uo) <= SOLVE_TOL
+        assert rel(u.detach().cpu().numpy().T, uo) <= SOLVE_TOL
         assert rel(k_t.grad.cpu().numpy(), go) <= SOLVE_TOL
-        assert rel(b_t.grad.cpu().numpy(), lam_o) <= SOLVE_TOL
+        assert rel(b_t.grad.cpu().numpy().T, lam_o) <= SOLVE_TOL
     finally:
         c.close()
 
@@ -50,8 +51,8 @@ def test_gradient_matches_finite_differences():
     from paper_2004_06722_amd.autograd import mass_norm_loss, poisson_solve
     c, kap, b, ut, _ = setup_case(p=4, grid=(2, 2, 3))
     try:
-        b_t = torch.tensor(b, device="cuda")
-        ut_t = torch.tensor(ut, device="cuda")
+        b_t = torch.tensor(b.T.copy(), device="cuda")
+        ut_t = torch.tensor(ut.T.copy(), device="cuda")
         k_t = torch.tensor(kap, device="cuda", requires_grad=True)
         L = mass_norm_loss(c.op, poisson_solve(c.op, k_t, b_t, rtol=1e-14), ut_t)
         L.backward()

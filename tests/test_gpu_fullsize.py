@@ -40,10 +40,11 @@ def sample_nodes(mesh, count, seed):
 def sampled_check(bp, N, k, ncomp=1, which=STIFF, count=48):
     op, mesh, grid, dirich = build(bp, N, k, ncomp)
     try:
-        u = synth.rhs_uniform(mesh.nglobal, 11, ncomp=ncomp)
-        w = op.apply(which, torch.from_numpy(u).cuda(), masked=dirich is not None)
+        u = synth.rhs_uniform(mesh.nglobal, 11, ncomp=ncomp)      # [n] or [n, ncomp]
+        w = op.apply(which, torch.from_numpy(np.ascontiguousarray(u.T)).cuda(),
+                     masked=dirich is not None)                  # [ncomp, n] on the device
         nodes = sample_nodes(mesh, count, 5)
-        wg = w[torch.from_numpy(nodes).cuda()].cpu().numpy()
+        wg = w[..., torch.from_numpy(nodes).cuda()].cpu().numpy().T
         rule = bp_rule(bp, N)
         els = elements_containing(mesh.elem_dofs, nodes)
         xyz = synth.element_coordinates(*grid, N, rule.xi, els, seed=0)
@@ -112,7 +113,8 @@ def test_grad_kappa_n5_e32cube_sampled():
     try:
         lam = synth.rhs_uniform(mesh.nglobal, 200, ncomp=8, dirichlet=mesh.boundary)
         u = synth.rhs_uniform(mesh.nglobal, 300, ncomp=8, dirichlet=mesh.boundary)
-        g = op.grad_kappa(torch.from_numpy(lam).cuda(), torch.from_numpy(u).cuda())
+        g = op.grad_kappa(torch.from_numpy(np.ascontiguousarray(lam.T)).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(u.T)).cuda())
         els = np.unique(np.random.default_rng(3).choice(mesh.elem_dofs.shape[0], 24, replace=False))
         gg = g[torch.from_numpy(els).cuda()].cpu().numpy()
         rule = bp_rule(5, 5)

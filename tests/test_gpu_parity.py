@@ -19,10 +19,19 @@ torch = pytest.importorskip("torch")
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    """Vector to the device: the oracle's [n, ncomp] becomes [ncomp, n]."""
+    a = np.asarray(a)
+    return torch.from_numpy(np.ascontiguousarray(a.T if a.ndim == 2 else a)).to("cuda")
 
 
 def host(t):
+    """Vector back to the oracle's layout [n, ncomp]."""
+    torch.cuda.synchronize()
+    a = t.cpu().numpy()
+    return a.T if a.ndim == 2 else a
+
+
+def host_array(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
 
@@ -100,6 +109,27 @@ def test_fp32_apply_matches_single_precision_oracle():
 def manufactured_rhs(c):
     f = synth.manufactured_f(c.mesh.global_coords())
     return c.disc.apply(MASS, f, masked=False) * c.disc.mask
+
+
+@pytest.mark.parametrize("bp,p,ncomp", [(5, 2, 1), (5, 4, 1), (5, 5, 1), (5, 6, 2), (5, 7, 1),
+                                         (5, 5, 8), (3, 4, 1), (3, 6, 1), (1, 5, 1)])
+def test_pcg_iterates_match_oracle_orders(bp, p, ncomp):
+    # every order's thread plane (including planes that leave idle lanes in a
+    # wave) and several components: the fused energy p.Ap drives alpha
+    c = Case(bp, p, *grid_for(p), seed=21, ncomp=ncomp)
+    try:
+        which = MASS if bp == 1 else STIFF
+        mask = (1 - c.mesh.boundary) if bp >= 3 else np.ones(c.disc.nglobal)
+        b = c.vec(3) * (mask[:, None] if ncomp > 1 else mask)
+        rec = []
+        A = lambda v: c.disc.apply(which, v, masked=bp >= 3)
+        pcg(A, b, c.disc.jacobi_inverse(which, masked=bp >= 3), maxit=8, fixed_iters=True,
+            record=rec)
+        for k in (1, 4, 8):
+            x, st = c.op.pcg_solve(dev(b), which=which, maxit=k, fixed_iters=True)
+            assert rel(host(x), rec[k - 1]) <= TOL, (k, rel(host(x), rec[k - 1]))
+    finally:
+        c.close()
 
 
 def test_pcg_iterates_match_oracle_config1():
@@ -190,11 +220,11 @@ def test_grad_kappa_matches_oracle():
         kap = synth.kappa_log(quad_points(c.disc.rule, c.mesh.node_xyz), 3)
         lam = c.vec(1) * (1 - c.mesh.boundary)[:, None]
         u = c.vec(2) * (1 - c.mesh.boundary)[:, None]
-        g = host(c.op.grad_kappa(dev(lam), dev(u)))
+        g = host_array(c.op.grad_kappa(dev(lam), dev(u)))
         ref = adjoint.grad_kappa(c.disc, lam, u)
         assert rel(g, ref) <= TOL
         # kappa-scaled operator
-        c.op.set_coeff(dev(kap))
+        c.op.set_coeff(torch.from_numpy(np.ascontiguousarray(kap)).cuda())  # [nelem, q^3]
         c.disc.kappa = kap
         w = host(c.op.apply(STIFF, dev(u)))
         assert rel(w, c.disc.apply(STIFF, u)) <= TOL
