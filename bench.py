@@ -32,7 +32,7 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0):
+def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0, fp32: bool = False):
     import numpy as np
     import torch
 
@@ -43,7 +43,8 @@ def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0):
     xi, _ = B.rule(N + 1, B.GLL)
     mesh = synth.brick_mesh(ex, ey, ez, N, xi, seed=0)
     dirich = mesh.boundary if bp >= 3 else None
-    op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp)
+    op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp,
+                    fp32=fp32)
     b = synth.rhs_uniform(mesh.nglobal, seed, ncomp=ncomp, dirichlet=dirich)
     bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()     # component-major
     info = {"E": ex * ey * ez, "grid": [ex, ey, ez], "n": N ** 3 * ex * ey * ez,
@@ -218,7 +219,8 @@ def manufactured_problem(N, grid, fp32):
 
 
 def workload_mixed(args):
-    """FP32-inner defect correction against FP64 PCG, both to 1e-10."""
+    """FP32-inner defect correction against FP64 PCG, both to 1e-10, for several
+    inner tolerances (1e-5 is the configured one)."""
     import torch
     grid = synth_grid(18)
     op, b, ue, nu = manufactured_problem(7, grid, fp32=True)
@@ -229,21 +231,29 @@ def workload_mixed(args):
     x64, st64 = op.pcg_solve(b, rtol=1e-10, maxit=100000)
     torch.cuda.synchronize()
     t64 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    xm, stm = op.pcg_solve_mixed(b, outer_rtol=1e-10, inner_rtol=1e-5, max_outer=50,
-                                 max_inner=100000)
-    torch.cuda.synchronize()
-    tm = time.perf_counter() - t0
+    log(f"FP64 PCG: {st64['iters']} iterations, {t64:.2f} s")
+    runs = []
+    for inner in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xm, stm = op.pcg_solve_mixed(b, outer_rtol=1e-10, inner_rtol=inner, max_outer=100,
+                                     max_inner=100000)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        runs.append({"inner_rtol": inner, "seconds": tm, "outer": stm["outer"],
+                     "inner_iters": stm["iters"], "rel_res": stm["rel_res"][0],
+                     "converged": stm["converged"], "speedup_vs_fp64": t64 / tm,
+                     "max_err_vs_exact": (xm - ue).abs().max().item(),
+                     "rel_diff_vs_fp64": ((xm - x64).norm() / x64.norm()).item()})
+        log(f"mixed inner {inner:.0e}: {stm['outer']} outer, {stm['iters']} inner, "
+            f"{tm:.2f} s, speedup {t64 / tm:.2f}")
     rec = {"workload": "BP5 N=7 E=64x64x64 manufactured solution sin(pi x)sin(pi y)sin(pi z), "
-                       "rhs = M f; FP64 Jacobi-PCG vs FP32-inner (rtol 1e-5) FP64 defect "
-                       "correction, both to relative residual 1e-10",
+                       "rhs = M f; FP64 Jacobi-PCG vs FP32-inner FP64 defect correction, both "
+                       "to relative residual 1e-10",
            "fp64": {"seconds": t64, "iters": st64["iters"], "rel_res": st64["rel_res"][0],
                     "max_err_vs_exact": (x64 - ue).abs().max().item()},
-           "mixed": {"seconds": tm, "outer": stm["outer"], "inner_iters": stm["iters"],
-                     "rel_res": stm["rel_res"][0],
-                     "max_err_vs_exact": (xm - ue).abs().max().item()},
-           "speedup": t64 / tm,
-           "rel_diff_mixed_vs_fp64": ((xm - x64).norm() / x64.norm()).item()}
+           "mixed": runs,
+           "best_speedup": max(r["speedup_vs_fp64"] for r in runs)}
     op.close()
     return rec
 
@@ -333,7 +343,7 @@ def workload_sweep13(args):
     r_max and n_0.8 per (BP, N)."""
     out = []
     cap = 4e7
-    for bp in (1, 3):
+    for bp in args.sweep_bp:
         for N in range(1, 9):
             pts = []
             for k in range(0, 30):
@@ -366,7 +376,10 @@ def main():
     ap.add_argument("--sweep-k", default="5:17", help="sweep E = 2^k for k in lo:hi")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run only the counter calibration copy")
+    ap.add_argument("--fp32-iters", type=int, default=0,
+                    help="profiling aid: also run this many FP32 inner CG iterations")
     ap.add_argument("--fd-directions", type=int, default=32, help="adjoint workload: FD directions")
+    ap.add_argument("--sweep-bp", type=int, nargs="+", default=[1, 3], help="sweep13: which BPs")
     ap.add_argument("--workload", default="bp5",
                     choices=["bp5", "vector", "mixed", "adjoint", "sweep13"],
                     help="bp5: the headline line; the others print their own record")
@@ -400,6 +413,13 @@ def main():
     log(f"setup done in {time.perf_counter() - t0:.1f} s: n={info['n']} unique={info['n_unique']}")
     op.set_option(BP_OPT_TIME_APPLY, 1)
     wall, st = time_solve(op, b, args.steps, args.warmup)
+    if args.fp32_iters:
+        op.close()
+        op, b, info = build_problem(bp, N, k, fp32=True)
+        op.pcg_solve_mixed(b, outer_rtol=0.0, inner_rtol=0.0, max_outer=1,
+                           max_inner=args.fp32_iters)
+        torch.cuda.synchronize()
+        log(f"ran {args.fp32_iters} FP32 inner iterations")
     log(f"timed {args.steps} iterations: wall {wall * 1e3:.2f} ms, loop {st['ms']:.2f} ms")
     n, E = info["n"], info["E"]
     value = args.steps * n / wall

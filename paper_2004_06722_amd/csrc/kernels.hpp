@@ -476,61 +476,64 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nelem, int p1, int q, int 
   double *sd = t2 + q * p1 * p1;   // [k][j][i]      p1^3
   double *sJ = sd + n3;            // q x p1
   double *sD = sJ + q * p1;        // q x p1
-  const int64_t e = blockIdx.x;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int x = t; x < q * p1; x += nt) {
     sJ[x] = basis[x];
     sD[x] = basis[q * p1 + x];
   }
-  for (int x = t; x < n3; x += nt) sd[x] = 0.0;
   const int nterms = stiff ? 6 : 1;
   const int pm[6] = {0, 0, 0, 1, 1, 2}, pn[6] = {0, 1, 2, 1, 2, 2};
-  __syncthreads();
-  for (int term = 0; term < nterms; ++term) {
-    const double *src = stiff ? Gm + (e * 6 + term) * q3 : Gm + e * q3;
-    for (int x = t; x < q3; x += nt) sg[x] = src[x];
-    const int m0 = stiff ? pm[term] : -1, m1 = stiff ? pn[term] : -1;
-    const double fac = (stiff && m0 != m1) ? 2.0 : 1.0;
+  // elements in a grid-stride loop (the grid is capped on the host)
+  for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
+    for (int x = t; x < n3; x += nt) sd[x] = 0.0;
     __syncthreads();
-    // direction dir uses F(m0,dir) * F(m1,dir), F = D if m == dir else J
-    for (int x = t; x < q * q * p1; x += nt) {
-      const int i = x % p1, bb = (x / p1) % q, c = x / (p1 * q);
-      double s = 0.0;
-      for (int a = 0; a < q; ++a) {
-        const double f0 = (m0 == 0 ? sD : sJ)[a * p1 + i];
-        const double f1 = (m1 == 0 ? sD : sJ)[a * p1 + i];
-        s += f0 * f1 * sg[(c * q + bb) * q + a];
+    for (int term = 0; term < nterms; ++term) {
+      const double *src = stiff ? Gm + (e * 6 + term) * q3 : Gm + e * q3;
+      for (int x = t; x < q3; x += nt) sg[x] = src[x];
+      const int m0 = stiff ? pm[term] : -1, m1 = stiff ? pn[term] : -1;
+      const double fac = (stiff && m0 != m1) ? 2.0 : 1.0;
+      __syncthreads();
+      // direction dir uses F(m0,dir) * F(m1,dir), F = D if m == dir else J
+      for (int x = t; x < q * q * p1; x += nt) {
+        const int i = x % p1, bb = (x / p1) % q, c = x / (p1 * q);
+        double s = 0.0;
+        for (int a = 0; a < q; ++a) {
+          const double f0 = (m0 == 0 ? sD : sJ)[a * p1 + i];
+          const double f1 = (m1 == 0 ? sD : sJ)[a * p1 + i];
+          s += f0 * f1 * sg[(c * q + bb) * q + a];
+        }
+        t1[x] = s;
       }
-      t1[x] = s;
-    }
-    __syncthreads();
-    for (int x = t; x < q * p1 * p1; x += nt) {
-      const int i = x % p1, j = (x / p1) % p1, c = x / (p1 * p1);
-      double s = 0.0;
-      for (int bb = 0; bb < q; ++bb) {
-        const double f0 = (m0 == 1 ? sD : sJ)[bb * p1 + j];
-        const double f1 = (m1 == 1 ? sD : sJ)[bb * p1 + j];
-        s += f0 * f1 * t1[(c * q + bb) * p1 + i];
+      __syncthreads();
+      for (int x = t; x < q * p1 * p1; x += nt) {
+        const int i = x % p1, j = (x / p1) % p1, c = x / (p1 * p1);
+        double s = 0.0;
+        for (int bb = 0; bb < q; ++bb) {
+          const double f0 = (m0 == 1 ? sD : sJ)[bb * p1 + j];
+          const double f1 = (m1 == 1 ? sD : sJ)[bb * p1 + j];
+          s += f0 * f1 * t1[(c * q + bb) * p1 + i];
+        }
+        t2[x] = s;
       }
-      t2[x] = s;
+      __syncthreads();
+      for (int x = t; x < n3; x += nt) {
+        const int i = x % p1, j = (x / p1) % p1, k = x / (p1 * p1);
+        double s = 0.0;
+        for (int c = 0; c < q; ++c) {
+          const double f0 = (m0 == 2 ? sD : sJ)[c * p1 + k];
+          const double f1 = (m1 == 2 ? sD : sJ)[c * p1 + k];
+          s += f0 * f1 * t2[(c * p1 + j) * p1 + i];
+        }
+        sd[x] += fac * s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int x = t; x < n3; x += nt) {
-      const int i = x % p1, j = (x / p1) % p1, k = x / (p1 * p1);
-      double s = 0.0;
-      for (int c = 0; c < q; ++c) {
-        const double f0 = (m0 == 2 ? sD : sJ)[c * p1 + k];
-        const double f1 = (m1 == 2 ? sD : sJ)[c * p1 + k];
-        s += f0 * f1 * t2[(c * p1 + j) * p1 + i];
-      }
-      sd[x] += fac * s;
+      const int v = idx[e * n3 + x];
+      const int g = decode_index(v, true, masked);
+      if (g >= 0) atomic_add(d + g, sd[x]);
     }
-    __syncthreads();
-  }
-  for (int x = t; x < n3; x += nt) {
-    const int v = idx[e * n3 + x];
-    const int g = decode_index(v, true, masked);
-    if (g >= 0) atomic_add(d + g, sd[x]);
+    __syncthreads();  // sd is cleared for the next element
   }
 }
 

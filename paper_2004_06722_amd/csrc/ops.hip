@@ -95,6 +95,8 @@ bool kernels_cover(int p, int q, int quad) {
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s) {
   int rc;
+  if (apply_blocks(op) * 128 >= (int64_t(1) << 32))
+    return set_error(BP_ERR_ARG, "mesh too large for one operator launch (work-items >= 2^32)");
   if (f32) {
     const float *G = op->kappa_set ? op->Gk32 : op->G32;
     rc = dispatch<float>(op, which, G, op->Bt32, op->basis32, (const float *)u, (float *)w,
@@ -116,7 +118,8 @@ int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_
                       (size_t)p1 * p1 * p1 + 2 * (size_t)q * p1);
   const bool stiff = which == BP_STIFF;
   const double *Gm = stiff ? (op->kappa_set ? op->Gk : op->G) : op->Bt;
-  hipLaunchKernelGGL(k_diag, dim3(op->nelem), dim3(256), lds, s, op->nelem, p1, q, stiff ? 1 : 0,
+  const int64_t grid = op->nelem < 65536 ? op->nelem : 65536;
+  hipLaunchKernelGGL(k_diag, dim3(grid), dim3(256), lds, s, op->nelem, p1, q, stiff ? 1 : 0,
                      op->idx, Gm, op->basis_d, d, masked ? 1 : 0);
   BP_HIP(hipGetLastError());
   return BP_OK;
