@@ -57,7 +57,8 @@ struct DevScalars {
   int breakdown;  // p.Ap < 0 seen
   int nonfinite;  // NaN/Inf in a reduction
   int fixed;      // fixed-iteration mode: never set done
-  int pad_[3];
+  int halted;     // set one iteration after done: the last x update has run
+  int pad_[2];
 };
 
 }  // namespace bp

@@ -184,9 +184,9 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
       if (rc) return rc;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
       cg_fin_alpha(nc, op->part, nb_apply, op->sc, s);
-      cg_update_xr<T>(nc, n, x, p, r, w, dinv, op->part, op->sc, s);
+      cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s);
       cg_fin_beta(nc, nb_vec, op->part, op->sc, s);
-      cg_update_p<T>(nc, n, p, r, dinv, op->sc, s);
+      cg_update_xp<T>(nc, n, x, p, r, dinv, op->sc, s);
     }
     BP_HIP(hipGetLastError());
     it += chunk;

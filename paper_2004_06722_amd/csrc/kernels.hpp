@@ -260,198 +260,263 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
 }
 
 // ---------------------------------------------------------------------------
-// BK1-BK4: Gauss-Legendre quadrature (q > p1). Interpolate to the quadrature
-// points first (u~ = J u), differentiate there with the q x q matrix D~
-// (section 5, eq. (gradr2)-(gradt2)), apply G (stiffness) or B~ (mass), and
-// return with the transposed operations. Every stage is one 1D contraction
-// between padded q x q x q LDS tiles, so a lane holds only one line of values
-// at a time and registers stay free for the G column, which (with the gather
-// map) is requested at entry. Thread (a, b) of the q x q plane owns the
-// quadrature column (a, b, .); lanes with a, b < p1 also own node column
-// (a, b, .). The local energy is accumulated at the quadrature points.
+// BK1-BK4: Gauss-Legendre quadrature with q = p1 + 1 points per direction.
+// Thread (a, b) of a q x q plane owns the quadrature column (a, b, .) and
+// keeps it in registers, so every contraction along t is register-only; the
+// r and s contractions go through padded LDS tiles. Lanes with a, b < p1
+// also own node column (a, b, .) for the gather and the scatter.
+// Stiffness (section 5, eq. (gradr2)-(gradt2) with shared partial sums):
+//   u_t = J^_t u, then J^_s and D^_s of it, then J^_r and D^_r of those give
+//   the interpolated values x, u_r and u_s; u_t = D~_t x along the column,
+// where D^ = D~ J^ is the derivative of the nodal basis at the Gauss points.
+// Then v = G (u_r, u_s, u_t) and the transposed chain back to the nodes.
+// Mass: J^ along t, s, r, then B~, then J^T along r, s, t.
+// Several elements share a work-group of up to 256 threads so that few lanes
+// idle; the G (or B~) column and the gather map are requested at entry. The
+// local energy is accumulated at the quadrature points. One component per
+// launch (u and w point at component c0): keeping G live across a loop over
+// components would cost the registers that the later stages reuse.
 // ---------------------------------------------------------------------------
+// Scheduling fence between the quadrature levels of a stage: without it the
+// scheduler issues the LDS reads of every level at once and the lane runs out
+// of registers (the values already loaded, such as basis rows, stay live).
+__device__ __forceinline__ void level_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Materialise a value where it is computed: the compiler may not sink its
+// arithmetic to a later use and keep all the loaded inputs live instead.
+__device__ __forceinline__ double pin(double v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ float pin(float v) {
+  __asm__ volatile("" : "+v"(v));
+  return v;
+}
+
+template <int Q>
+struct QPlane {
+  static constexpr int N = Q * Q;
+  static constexpr int EPB = N >= 256 ? 1 : 256 / N;
+  static constexpr int USED = EPB * N;
+  static constexpr int THREADS = ((USED + 63) / 64) * 64;
+};
+
 template <int P1, int Q, typename T, bool STIFF>
-__global__ __launch_bounds__((Plane<P1, Q>::THREADS)) void k_op_interp(
+__global__ __launch_bounds__((QPlane<Q>::THREADS), 2) void k_op_interp(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
-    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int64_t cstride,
-    int ncomp, int masked, double *__restrict__ part, const int *__restrict__ done) {
-  using PL = Plane<P1, Q>;
-  constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QQ = Q * Q, QP = Q + 1;
+    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
+    int masked, double *__restrict__ part, const int *__restrict__ done) {
+  using PL = QPlane<Q>;
+  constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QQ = Q * Q;
+  constexpr int RP = Q + 1;       // tile row: q entries and one pad entry
+  constexpr int TS = QQ * RP;     // tile [c][b][0..RP)
   constexpr int NG = STIFF ? 6 : 1;
-  constexpr int NT = STIFF ? 4 : 3;  // LDS tiles
-  static_assert(Q > P1, "interpolating kernel expects q > p1");
+  constexpr int NT = STIFF ? 3 : 2;
+  static_assert(Q == P1 + 1, "interpolating kernel expects q = p1 + 1");
   if (done && *done) return;
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
-  const int slot = act ? t / PL::N : 0;
-  const int ab = t % PL::N;
-  const int a = ab % Q, b = ab / Q;
+  // Lanes past the last plane act as column a = q of plane 0: their tile
+  // stores land in the pad entries, which are never read, so no store needs
+  // a guard. Columns a, b >= p1 of the node-indexed stages are written but
+  // not read either.
+  const int slot = act ? t / QQ : 0;
+  const int a = act ? t % Q : Q;
+  const int b = act ? (t % QQ) / Q : 0;
+  const int ab = act ? t % QQ : 0;
+  const int at = a < Q ? a : Q - 1;         // row of the basis tables
+  const int ic = a < P1 ? a : P1 - 1;       // node index along r (clamped)
+  const int jc = b < P1 ? b : P1 - 1;       // node index along s (clamped)
   const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
-  if (PL::EPB == 1 && e >= nelem) return;  // uniform over the work-group
   const bool live = act && e < nelem;
-  const int64_t ec = live ? e : nelem - 1;
-  const bool own = live && a < P1 && b < P1;  // owns node column (i=a, j=b)
+  const int64_t ec = live ? e : nelem - 1;  // element whose data the lane reads
 
-  __shared__ T sJ[Q][P1 + 1];   // sJ[a][i]  = J^[a][i]
-  __shared__ T sJt[P1][QP];     // sJt[i][a] = J^[a][i]
-  __shared__ T sDq[Q][QP];      // sDq[a][m] = D~[a][m]
-  __shared__ T sDqt[Q][QP];     // sDqt[m][a] = D~[a][m]
-  __shared__ T tile[NT][PL::EPB][Q][Q][QP];
+  __shared__ T sJ[Q][P1];  // J^[a][i]
+  __shared__ T sD[Q][P1];  // D^[a][i]
+  __shared__ T tile[PL::EPB][NT][TS];
+  T *const A = tile[slot][0];
+  T *const B = tile[slot][1];
+  T *const C = tile[slot][NT - 1];  // third tile (stiffness only)
+  const int row = b * RP;           // offset of the lane's row in a level
 
-  // one round trip: gather map (node columns) and G / B~ (quadrature columns)
+  // one round trip: node column of the gather map, quadrature column of G / B~
   int gk[P1];
-  T mk[P1];
-  const int ia = a < P1 ? a : 0, jb = b < P1 ? b : 0;
 #pragma unroll
-  for (int k = 0; k < P1; ++k) gk[k] = idx[ec * N3 + ia + P1 * (jb + P1 * k)];
+  for (int k = 0; k < P1; ++k) gk[k] = idx[ec * N3 + ic + P1 * (jc + P1 * k)];
   T g[NG][Q];
   const T *Ge = Gm + ec * NG * NQ + ab;
 #pragma unroll
   for (int c = 0; c < Q; ++c)
 #pragma unroll
     for (int n = 0; n < NG; ++n) g[n][c] = __builtin_nontemporal_load(Ge + n * NQ + c * QQ);
+  // bit k of mb: node k of the column is gathered and scattered
+  unsigned mb = 0;
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
     const int v = gk[k];
-    mk[k] = (own && (v >= 0 || !masked)) ? T(1) : T(0);
+    if (live && a < P1 && b < P1 && (v >= 0 || !masked)) mb |= 1u << k;
     gk[k] = v >= 0 ? v : -1 - v;
   }
   for (int x = t; x < Q * P1; x += PL::THREADS) {
-    const T v = basis[x];
-    sJ[x / P1][x % P1] = v;
-    sJt[x % P1][x / P1] = v;
+    sJ[x / P1][x % P1] = basis[x];
+    sD[x / P1][x % P1] = basis[Q * P1 + x];
   }
-  for (int x = t; x < QQ; x += PL::THREADS) {
-    const T v = basis[2 * Q * P1 + x];
-    sDq[x / Q][x % Q] = v;
-    sDqt[x % Q][x / Q] = v;
-  }
-  T(&A)[Q][Q][QP] = tile[0][slot];
-  T(&B)[Q][Q][QP] = tile[1][slot];
-  T(&C)[Q][Q][QP] = tile[2][slot];
+  const T *Jg = basis;               // J^[c][k] at c * P1 + k (uniform reads)
+  const T *Dq = basis + 2 * Q * P1;  // D~[c][m] at c * Q + m
 
-  for (int comp = 0; comp < ncomp; ++comp) {
-    // gather: A[k][j][i] = u
+  {
+    // gather; interpolate along t in registers: A[c][j][i] = sum_k J^[c][k] u(i, j, k)
+    T uk[P1];
 #pragma unroll
     for (int k = 0; k < P1; ++k) {
-      const T val = u[gk[k] + comp * cstride] * mk[k];
-      if (act && a < P1 && b < P1) A[k][b][a] = val;
+      const T v = u[gk[k]];
+      uk[k] = (mb >> k & 1u) ? v : T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < P1; ++k) s += Jg[c * P1 + k] * uk[k];
+      A[(c * Q) * RP + row + a] = s;
     }
     __syncthreads();
-    // interpolate along r: B[k][j][a] = sum_i J[a][i] A[k][j][i]   (b plays j)
-    if (act && b < P1)
+    // along s (lane (i, b)): B[c][b][i] = sum_j J^[b][j] A[c][j][i]; C with D^
 #pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        T s = 0;
+    for (int c = 0; c < Q; ++c) {
+      T s0 = 0, s1 = 0;
 #pragma unroll
-        for (int m = 0; m < P1; ++m) s += sJ[a][m] * A[k][b][m];
-        B[k][b][a] = s;
+      for (int j = 0; j < P1; ++j) {
+        const T v = A[(c * Q + j) * RP + a];
+        s0 += sJ[b][j] * v;
+        if constexpr (STIFF) s1 += sD[b][j] * v;
       }
+      B[(c * Q) * RP + row + a] = s0;
+      if constexpr (STIFF) C[(c * Q) * RP + row + a] = s1;
+      level_fence();
+    }
     __syncthreads();
-    // along s: A[k][b][a] = sum_j J[b][j] B[k][j][a]
-    if (act)
+    // along r: the column's interpolated values x
+    T x[Q];
 #pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        T s = 0;
+    for (int c = 0; c < Q; ++c) {
+      T s0 = 0;
 #pragma unroll
-        for (int m = 0; m < P1; ++m) s += sJ[b][m] * B[k][m][a];
-        A[k][b][a] = s;
-      }
-    __syncthreads();
-    // along t: B[c][b][a] = sum_k J[c][k] A[k][b][a]
+      for (int i = 0; i < P1; ++i) s0 += sJ[at][i] * B[(c * Q) * RP + row + i];
+      x[c] = pin(s0);
+      level_fence();
+    }
     double en = 0.0;
-    if (act) {
-      T col[P1];
-#pragma unroll
-      for (int k = 0; k < P1; ++k) col[k] = A[k][b][a];
+    T S[Q];  // column after the transposed r and s contractions
+    if constexpr (STIFF) {
+      // per level: u_r, u_s along r, u_t along the column, G, energy;
+      // v_r into A (free since the s stage), v_s and v_t kept for later
+      T vsk[Q], vtk[Q];
 #pragma unroll
       for (int c = 0; c < Q; ++c) {
-        T s = 0;
+        T r0 = 0, s0 = 0, ut = 0;
 #pragma unroll
-        for (int k = 0; k < P1; ++k) s += sJ[c][k] * col[k];
-        if constexpr (STIFF) {
-          B[c][b][a] = s;
-        } else {
-          const T v = g[0][c] * s;  // B~ at the point
-          en += (double)s * (double)v;
-          B[c][b][a] = v;
+        for (int i = 0; i < P1; ++i) {
+          r0 += sD[at][i] * B[(c * Q) * RP + row + i];
+          s0 += sJ[at][i] * C[(c * Q) * RP + row + i];
         }
+#pragma unroll
+        for (int m = 0; m < Q; ++m) ut += Dq[c * Q + m] * x[m];
+        const T vr = g[0][c] * r0 + g[1][c] * s0 + g[2][c] * ut;
+        const T vs = g[1][c] * r0 + g[3][c] * s0 + g[4][c] * ut;
+        const T vt = g[2][c] * r0 + g[4][c] * s0 + g[5][c] * ut;
+        if (live) en += (double)r0 * (double)vr + (double)s0 * (double)vs + (double)ut * (double)vt;
+        A[(c * Q) * RP + row + a] = vr;
+        vsk[c] = pin(vs);
+        vtk[c] = pin(vt);
+        level_fence();
       }
-    }
-    __syncthreads();
-    if constexpr (STIFF) {
-      T(&Dt)[Q][Q][QP] = tile[3][slot];
-      // derivatives at the quadrature points, G, into A (r), C (s), Dt (t)
-      if (act)
+      // z = D~^T v_t along the column (values-space part of the t term)
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-          T ur = 0, us = 0, ut = 0;
+      for (int c = 0; c < Q; ++c) {
+        T s0 = 0;
 #pragma unroll
-          for (int m = 0; m < Q; ++m) {
-            ur += sDq[a][m] * B[c][b][m];
-            us += sDq[b][m] * B[c][m][a];
-            ut += sDq[c][m] * B[m][b][a];
-          }
-          const T vr = g[0][c] * ur + g[1][c] * us + g[2][c] * ut;
-          const T vs = g[1][c] * ur + g[3][c] * us + g[4][c] * ut;
-          const T vt = g[2][c] * ur + g[4][c] * us + g[5][c] * ut;
-          en += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
-          A[c][b][a] = vr;
-          C[c][b][a] = vs;
-          Dt[c][b][a] = vt;
-        }
+        for (int m = 0; m < Q; ++m) s0 += Dq[m * Q + c] * vtk[m];
+        x[c] = s0;
+      }
+      __syncthreads();  // B and C have been read
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        B[(c * Q) * RP + row + a] = vsk[c];
+        C[(c * Q) * RP + row + a] = x[c];
+      }
       __syncthreads();
-      // transposed derivatives into B
-      if (act)
+      // back along r (lane (i, b)): P = D^T v_r + J^T z, R = J^T v_s
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-          T s = 0;
+      for (int c = 0; c < Q; ++c) {
+        T s0 = 0, s1 = 0;
 #pragma unroll
-          for (int m = 0; m < Q; ++m) {
-            s += sDqt[a][m] * A[c][b][m];
-            s += sDqt[b][m] * C[c][m][a];
-            s += sDqt[c][m] * Dt[m][b][a];
-          }
-          B[c][b][a] = s;
+        for (int m = 0; m < Q; ++m) {
+          const int o = (c * Q) * RP + row + m;
+          s0 += sD[m][ic] * A[o] + sJ[m][ic] * C[o];
+          s1 += sJ[m][ic] * B[o];
         }
+        vsk[c] = pin(s0);
+        vtk[c] = pin(s1);
+        level_fence();
+      }
       __syncthreads();
-    }
-    // transposed interpolation along t: A[k][b][a] = sum_c J[c][k] B[c][b][a]
-    if (act) {
-      T col[Q];
 #pragma unroll
-      for (int c = 0; c < Q; ++c) col[c] = B[c][b][a];
+      for (int c = 0; c < Q; ++c) {
+        A[(c * Q) * RP + row + a] = vsk[c];
+        B[(c * Q) * RP + row + a] = vtk[c];
+      }
+      __syncthreads();
+      // back along s (lane (i, j)): S = J^T P + D^T R
 #pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        T s = 0;
+      for (int c = 0; c < Q; ++c) {
+        T s0 = 0;
 #pragma unroll
-        for (int c = 0; c < Q; ++c) s += sJt[k][c] * col[c];
-        A[k][b][a] = s;
+        for (int m = 0; m < Q; ++m) {
+          const int o = (c * Q + m) * RP + ic;
+          s0 += sJ[m][jc] * A[o] + sD[m][jc] * B[o];
+        }
+        S[c] = pin(s0);
+        level_fence();
+      }
+    } else {
+      // B~ at the points, energy; values into A (free since the s stage)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const T v = g[0][c] * x[c];
+        if (live) en += (double)x[c] * (double)v;
+        A[(c * Q) * RP + row + a] = v;
+      }
+      __syncthreads();
+      // back along r (lane (i, b)) into B (read before the last barrier)
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        T s0 = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) s0 += sJ[m][ic] * A[(c * Q) * RP + row + m];
+        B[(c * Q) * RP + row + a] = s0;
+        level_fence();
+      }
+      __syncthreads();
+      // back along s (lane (i, j))
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        T s0 = 0;
+#pragma unroll
+        for (int m = 0; m < Q; ++m) s0 += sJ[m][jc] * B[(c * Q + m) * RP + ic];
+        S[c] = pin(s0);
+        level_fence();
       }
     }
-    __syncthreads();
-    // along s: C[k][j][a] = sum_b J[b][j] A[k][b][a]
-    if (act && b < P1)
+    // back along t in registers and scatter: w(i, j, k) += sum_c J^[c][k] S[c]
 #pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        T s = 0;
+    for (int k = 0; k < P1; ++k) {
+      T s = 0;
 #pragma unroll
-        for (int m = 0; m < Q; ++m) s += sJt[b][m] * A[k][m][a];
-        C[k][b][a] = s;
-      }
-    __syncthreads();
-    // along r and scatter: w(i,j,k) = sum_a J[a][i] C[k][j][a]
-    if (act && a < P1 && b < P1)
-#pragma unroll
-      for (int k = 0; k < P1; ++k) {
-        T s = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) s += sJt[a][m] * C[k][b][m];
-        if (mk[k] != T(0)) atomic_add(w + gk[k] + comp * cstride, s);
-      }
+      for (int c = 0; c < Q; ++c) s += Jg[c * P1 + k] * S[c];
+      if (mb >> k & 1u) atomic_add(w + gk[k], s);
+    }
     double enb[1] = {en};
-    if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + comp, 1);
-    __syncthreads();
+    if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + c0, 1);
   }
 }
 

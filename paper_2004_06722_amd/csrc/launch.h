@@ -17,12 +17,15 @@ int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, dou
 
 // vector kernels (vec.hip); sizes are global nodes n and components nc
 // CG vector kernels run one node per thread (vec_blocks); fills and
-// conversions use a capped grid-stride grid (grid_blocks). Block partial
-// sums are reduced to at most kStage2Rows rows before the final fixed-order
-// single-work-group sum; the stage-1 output sits right after the partials.
+// conversions use a capped grid-stride grid (grid_blocks). Up to
+// kDirectRows block partial sums go straight to the final fixed-order
+// single-work-group sum (one launch less per reduction on small meshes);
+// more are first folded to at most kStage2Rows rows, stored right after
+// the partials.
 constexpr int kVecThreads = 256;
 constexpr int64_t kVecMaxBlocks = 2048;
 constexpr int64_t kStage2Rows = 256;
+constexpr int64_t kDirectRows = 4096;
 int64_t vec_blocks(int64_t n);
 int64_t grid_blocks(int64_t n);
 void fill_f64(double *x, int64_t n, double v, hipStream_t s);
@@ -38,12 +41,12 @@ void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, dou
              DevScalars *sc, hipStream_t s);
 void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s);
 template <typename T>
-void cg_update_xr(int nc, int64_t n, T *x, const T *p, T *r, T *w, const T *dinv, double *part,
-                  DevScalars *sc, hipStream_t s);
+void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
+                 hipStream_t s);
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s);
 template <typename T>
-void cg_update_p(int nc, int64_t n, T *p, const T *r, const T *dinv, DevScalars *sc,
-                 hipStream_t s);
+void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
+                  hipStream_t s);
 
 // defect correction helpers (FP64 outer loop)
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,

@@ -7,8 +7,11 @@
 namespace bp {
 
 int64_t plane_epb(int p1, int q) {
-  const int m = p1 > q ? p1 : q;
-  const int n = m * m;
+  if (q > p1) {  // Gauss-Legendre kernels: q x q planes in up to 256 threads
+    const int n = q * q;
+    return n >= 256 ? 1 : 256 / n;
+  }
+  const int n = p1 * p1;
   return n >= 64 ? 1 : 64 / n;
 }
 
@@ -43,10 +46,12 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
 template <int P1, int Q, typename T, bool STIFF>
 int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int masked,
            double *part, const int *done, hipStream_t s) {
-  using PL = Plane<P1, Q>;
-  hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(apply_blocks(op)), dim3(PL::THREADS),
-                     0, s, op->nelem, op->idx, Gm, basis, u, w, op->nglobal, op->ncomp, masked,
-                     part, done);
+  using PL = QPlane<Q>;
+  static_assert(PL::EPB * Q * Q <= 256, "plane layout");
+  for (int c = 0; c < op->ncomp; ++c)
+    hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(apply_blocks(op)), dim3(PL::THREADS),
+                       0, s, op->nelem, op->idx, Gm, basis, u + c * op->nglobal,
+                       w + c * op->nglobal, op->ncomp, c, masked, part, done);
   return BP_OK;
 }
 
@@ -95,7 +100,9 @@ bool kernels_cover(int p, int q, int quad) {
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s) {
   int rc;
-  if (apply_blocks(op) * 128 >= (int64_t(1) << 32))
+  // work-group size: 256 for the Gauss-Legendre planes, whole waves of p1^2 else
+  const int64_t tpb = op->q > op->p1 ? 256 : ((op->p1 * op->p1 + 63) / 64) * 64;
+  if (apply_blocks(op) * tpb >= (int64_t(1) << 32))
     return set_error(BP_ERR_ARG, "mesh too large for one operator launch (work-items >= 2^32)");
   if (f32) {
     const float *G = op->kappa_set ? op->Gk32 : op->G32;

@@ -1,9 +1,10 @@
 // Streaming vector kernels of the Jacobi-PCG iteration (section 3; section 8
 // counts these updates as a few flops and memory words per DOF each) with
 // deterministic reductions: every work-group writes its partial sums, a
-// first stage folds them to at most 256 rows and a single work-group adds
-// those in a fixed order and updates alpha, beta and the convergence flag on
-// the device, so the host never waits inside the iteration.
+// first stage folds them to at most 256 rows when there are many, and a
+// single work-group adds the rows in a fixed order and updates alpha, beta
+// and the convergence flag on the device, so the host never waits inside
+// the iteration.
 #include <cmath>
 
 #include "bp_internal.h"
@@ -156,12 +157,16 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restri
     sc->breakdown = 0;
     sc->nonfinite = bad;
     sc->done = bad || (!sc->fixed && converged(sc, nc));
+    sc->halted = sc->done;  // x0 is already the answer
   }
 }
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restrict__ part,
                                                            int64_t nb, int nc, DevScalars *sc) {
-  if (sc->done) return;
+  if (sc->done) {
+    if (threadIdx.x == 0) sc->halted = 1;
+    return;
+  }
   __shared__ double res[kMaxComp];
   reduce_columns(part, nb, nc, res);
   if (threadIdx.x == 0)
@@ -174,11 +179,13 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
     }
 }
 
-// x += alpha p; r -= alpha w; w = 0; partials r.z (z = dinv r) and r.r.
+// r -= alpha w; w = 0; partials r.z (z = dinv r) and r.r. The matching
+// x += alpha p is deferred to k_cg_update_xp, which reads p anyway: five
+// vector words here and six there instead of eight and four.
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_cg_update_xr(
-    int64_t n, T *__restrict__ x, const T *__restrict__ p, T *__restrict__ r, T *__restrict__ w,
-    const T *__restrict__ dinv, double *__restrict__ part, const DevScalars *__restrict__ sc) {
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
+    int64_t n, T *__restrict__ r, T *__restrict__ w, const T *__restrict__ dinv,
+    double *__restrict__ part, const DevScalars *__restrict__ sc) {
   if (sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
@@ -187,7 +194,6 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xr(
     const int64_t f = comp * n + v;
     const T al = (T)sc->alpha[comp];
     const T di = dinv[v];
-    x[f] += al * p[f];
     const T rv = r[f] - al * w[f];
     r[f] = rv;
     w[f] = T(0);
@@ -216,17 +222,24 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restri
   }
 }
 
-// p = dinv r + beta p
+// x += alpha p with the p of this iteration, then p = dinv r + beta p unless
+// the iteration just converged. `halted` (set by the next k_fin_alpha once
+// done is seen) stops the x update in the launches queued after the last
+// iteration.
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_cg_update_p(int64_t n, T *__restrict__ p,
-                                                             const T *__restrict__ r,
-                                                             const T *__restrict__ dinv,
-                                                             const DevScalars *__restrict__ sc) {
-  if (sc->done) return;
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_xp(int64_t n, T *__restrict__ x,
+                                                              T *__restrict__ p,
+                                                              const T *__restrict__ r,
+                                                              const T *__restrict__ dinv,
+                                                              const DevScalars *__restrict__ sc) {
+  if (sc->halted) return;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   if (v < n) {
-    const int64_t f = blockIdx.y * n + v;
-    p[f] = dinv[v] * r[f] + (T)sc->beta[blockIdx.y] * p[f];
+    const int comp = blockIdx.y;
+    const int64_t f = comp * n + v;
+    const T pv = p[f];
+    x[f] += (T)sc->alpha[comp] * pv;
+    if (!sc->done) p[f] = dinv[v] * r[f] + (T)sc->beta[comp] * pv;
   }
 }
 
@@ -317,11 +330,12 @@ int64_t grid_blocks(int64_t n) {
   return b < 1 ? 1 : b;
 }
 
-// Reduce part[nb][width] to at most kStage2Rows rows in `stage`, then return
-// the pointer and row count the single-work-group finisher reads.
+// Reduce part[nb][width] to at most kStage2Rows rows in `stage` (nothing to
+// do up to kDirectRows rows), then return the pointer and row count the
+// single-work-group finisher reads.
 static const double *reduce_stage1(const double *part, int64_t nb, int width, double *stage,
                                    int64_t *rows, hipStream_t s) {
-  if (nb <= kStage2Rows) {
+  if (nb <= kDirectRows) {
     *rows = nb;
     return part;
   }
@@ -369,10 +383,10 @@ void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStr
 }
 
 template <typename T>
-void cg_update_xr(int nc, int64_t n, T *x, const T *p, T *r, T *w, const T *dinv, double *part,
-                  DevScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update_xr<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x,
-                     p, r, w, dinv, part, sc);
+void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
+                 hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update_r<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, r,
+                     w, dinv, part, sc);
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s) {
@@ -383,10 +397,10 @@ void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStre
 }
 
 template <typename T>
-void cg_update_p(int nc, int64_t n, T *p, const T *r, const T *dinv, DevScalars *sc,
-                 hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update_p<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, p,
-                     r, dinv, sc);
+void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update_xp<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x,
+                     p, r, dinv, sc);
 }
 
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,
@@ -406,13 +420,13 @@ template void cg_init<double>(int, int64_t, const double *, double *, double *, 
                               const double *, double *, DevScalars *, hipStream_t);
 template void cg_init<float>(int, int64_t, const float *, float *, float *, float *,
                              const float *, double *, DevScalars *, hipStream_t);
-template void cg_update_xr<double>(int, int64_t, double *, const double *, double *, double *,
-                                   const double *, double *, DevScalars *, hipStream_t);
-template void cg_update_xr<float>(int, int64_t, float *, const float *, float *, float *,
-                                  const float *, double *, DevScalars *, hipStream_t);
-template void cg_update_p<double>(int, int64_t, double *, const double *, const double *,
+template void cg_update_r<double>(int, int64_t, double *, double *, const double *, double *,
                                   DevScalars *, hipStream_t);
-template void cg_update_p<float>(int, int64_t, float *, const float *, const float *,
+template void cg_update_r<float>(int, int64_t, float *, float *, const float *, double *,
                                  DevScalars *, hipStream_t);
+template void cg_update_xp<double>(int, int64_t, double *, double *, const double *,
+                                   const double *, DevScalars *, hipStream_t);
+template void cg_update_xp<float>(int, int64_t, float *, float *, const float *, const float *,
+                                  DevScalars *, hipStream_t);
 
 }  // namespace bp

@@ -5,8 +5,9 @@ geometric factors (section 5 after eq. (gij): 6 q^3 words per element for the
 stiffness, q^3 for B~ of eq. (mass)), the int32 gather map (p1^3 per element;
 the global tensor layout may not be exploited, section 3), and the vectors.
 Vector words per DOF and iteration: the operator reads p and writes w (2),
-the CG update reads x, p, r, w, dinv and writes x, r (7), the direction
-update reads r, dinv, p and writes p (4): 13 in all. DOFs are n = p^3 E
+the CG updates move 11: the residual update reads r, w, dinv and writes r
+and the zeroed w for the next scatter (5), the solution and direction
+update reads x, p, r, dinv and writes x, p (6). 13 in all. DOFs are n = p^3 E
 (section 2) per component.
 
 Flops follow section 5: eq. (work2)/(work3) for the sum-factorised
