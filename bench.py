@@ -98,12 +98,23 @@ def cpu_baseline(N: int, target_s: float = 15.0):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device sources the traffic counters were taken on."""
+    """Hash of what the BK5 operator kernel is built from: kernels.hpp up to
+    the end of k_stiff_colloc (its helpers and the kernel), its launcher in
+    ops.hip and the compiler flags. Other kernels may change freely."""
     import hashlib
+    from paper_2004_06722_amd import build as bp_build
+    csrc = os.path.join(ROOT, "paper_2004_06722_amd", "csrc")
+    with open(os.path.join(csrc, "kernels.hpp")) as fh:
+        k = fh.read()
+    k = k[:k.index("// Mass with collocated GLL quadrature")]
+    with open(os.path.join(csrc, "ops.hip")) as fh:
+        o = fh.read()
+    a = o.index("int stiff_colloc(")
+    o = o[a:o.index("\n}\n", a)]
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "ops.hip"):
-        with open(os.path.join(ROOT, "paper_2004_06722_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    flags = [f for f in bp_build.common_flags() if not f.startswith("-I")]
+    for part in (k, o, " ".join(flags)):
+        h.update(part.encode())
     return h.hexdigest()[:16]
 
 
@@ -427,7 +438,7 @@ def main():
     ab = model.apply_bytes(bp, N, E)
     achieved = ab / (apply_avg_ms * 1e-3) / 1e9
     it_bytes = model.iteration_bytes(bp, N, E)
-    kname = f"k_stiff_colloc<{N + 1}, 1, double>"
+    kname = f"k_stiff_colloc<{N + 1}, double>"
     loop_s = st["ms"] * 1e-3
     result = {
         "metric": METRIC,

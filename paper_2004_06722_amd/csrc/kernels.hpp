@@ -93,7 +93,7 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // LDS. The k direction stays in registers; the r and s contractions go
 // through LDS tiles. Loads are branch-free: an element slot past the end
 // reads the last element and a Dirichlet node reads its (valid) global
-// entry, both scaled by a 0/1 mask. Entries of D^ with compile-time indices
+// entry, both masked. Entries of D^ with compile-time indices
 // are scalar loads from Dg (global memory, D^[a][m] at a * p1 + m); the
 // lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
 // accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
@@ -134,12 +134,13 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 #pragma unroll
     for (int n = 0; n < 6; ++n) g[n][k] = __builtin_nontemporal_load(Ge + n * N3 + k * PP);
 
-  // decode: global id and 0/1 mask (0 for dead slots and masked Dirichlet)
-  T mk[P1];
+  // decode: global id, and bit k of mb set when node k is gathered and
+  // scattered (clear for dead slots and masked Dirichlet nodes)
+  unsigned mb = 0;
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
     const int v = gk[k];
-    mk[k] = (live && (v >= 0 || !masked)) ? T(1) : T(0);
+    if (live && (v >= 0 || !masked)) mb |= 1u << k;
     gk[k] = v >= 0 ? v : -1 - v;
   }
 
@@ -148,7 +149,10 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int k = 0; k < P1; ++k) ru[c][k] = u[gk[k]] * mk[k];
+    for (int k = 0; k < P1; ++k) {
+      const T v = u[gk[k]];
+      ru[c][k] = (mb >> k & 1u) ? v : T(0);
+    }
   for (int x = t; x < PP; x += PL::THREADS) {
     sD[x / P1][x % P1] = Dg[x];
     sDt[x % P1][x / P1] = Dg[x];
@@ -211,7 +215,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
         acc += sDt[i][m] * sr[slot][c][k][j][m];
         acc += sDt[j][m] * ss[slot][c][k][m][i];
       }
-      if (mk[k] != T(0)) atomic_add(w + gk[k], acc);
+      if (mb >> k & 1u) atomic_add(w + gk[k], acc);
     }
   }
   if (part) block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0, 1);
