@@ -355,7 +355,7 @@ def workload_sweep13(args):
     out = []
     cap = 4e7
     for bp in args.sweep_bp:
-        for N in range(1, 9):
+        for N in args.sweep_n:
             pts = []
             for k in range(0, 30):
                 E = 2 ** k
@@ -391,6 +391,8 @@ def main():
                     help="profiling aid: also run this many FP32 inner CG iterations")
     ap.add_argument("--fd-directions", type=int, default=32, help="adjoint workload: FD directions")
     ap.add_argument("--sweep-bp", type=int, nargs="+", default=[1, 3], help="sweep13: which BPs")
+    ap.add_argument("--sweep-n", type=int, nargs="+", default=list(range(1, 9)),
+                    help="sweep13: which orders N")
     ap.add_argument("--workload", default="bp5",
                     choices=["bp5", "vector", "mixed", "adjoint", "sweep13"],
                     help="bp5: the headline line; the others print their own record")

@@ -154,7 +154,7 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   const int nc = op->ncomp;
   const int64_t n = op->nglobal, nv = n * nc;
   const bool masked = op->has_dirichlet;
-  const int64_t nb_apply = apply_blocks(op), nb_vec = vec_blocks(n);
+  const int64_t nb_apply = apply_rows(op, which), nb_vec = vec_blocks(n);
   int rc = upload_scalars(op, rtol, fixed, s);
   if (rc) return rc;
   if constexpr (sizeof(T) == 8)

@@ -297,25 +297,30 @@ __device__ __forceinline__ float pin(float v) {
   return v;
 }
 
-template <int Q>
+// VS: at q = 8 and q = 10 the stiffness kernel parks v_s in a fourth LDS
+// tile instead of registers (the register file would otherwise spill); the
+// larger LDS footprint then takes fewer elements per work-group.
+template <int Q, bool STIFF>
 struct QPlane {
+  static constexpr bool VS = STIFF && (Q == 8 || Q == 10);
+  static constexpr int NT = STIFF ? (VS ? 4 : 3) : 2;  // LDS tiles per element
   static constexpr int N = Q * Q;
-  static constexpr int EPB = N >= 256 ? 1 : 256 / N;
+  static constexpr int EPB = VS ? (Q == 8 ? 3 : 1) : (N >= 256 ? 1 : 256 / N);
   static constexpr int USED = EPB * N;
   static constexpr int THREADS = ((USED + 63) / 64) * 64;
 };
 
 template <int P1, int Q, typename T, bool STIFF>
-__global__ __launch_bounds__((QPlane<Q>::THREADS), 2) void k_op_interp(
+__global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
     const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
     int masked, double *__restrict__ part, const int *__restrict__ done) {
-  using PL = QPlane<Q>;
+  using PL = QPlane<Q, STIFF>;
   constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QQ = Q * Q;
   constexpr int RP = Q + 1;       // tile row: q entries and one pad entry
   constexpr int TS = QQ * RP;     // tile [c][b][0..RP)
   constexpr int NG = STIFF ? 6 : 1;
-  constexpr int NT = STIFF ? 3 : 2;
+  constexpr int NT = PL::NT;
   static_assert(Q == P1 + 1, "interpolating kernel expects q = p1 + 1");
   if (done && *done) return;
   const int t = threadIdx.x;
@@ -340,7 +345,8 @@ __global__ __launch_bounds__((QPlane<Q>::THREADS), 2) void k_op_interp(
   __shared__ T tile[PL::EPB][NT][TS];
   T *const A = tile[slot][0];
   T *const B = tile[slot][1];
-  T *const C = tile[slot][NT - 1];  // third tile (stiffness only)
+  T *const C = tile[slot][STIFF ? 2 : 1];  // third tile (stiffness only)
+  T *const V = tile[slot][NT - 1];         // v_s: fourth tile with PL::VS, else B
   const int row = b * RP;           // offset of the lane's row in a level
 
   // one round trip: node column of the gather map, quadrature column of G / B~
@@ -430,7 +436,10 @@ __global__ __launch_bounds__((QPlane<Q>::THREADS), 2) void k_op_interp(
         const T vt = g[2][c] * r0 + g[4][c] * s0 + g[5][c] * ut;
         if (live) en += (double)r0 * (double)vr + (double)s0 * (double)vs + (double)ut * (double)vt;
         A[(c * Q) * RP + row + a] = vr;
-        vsk[c] = pin(vs);
+        if constexpr (PL::VS)
+          V[(c * Q) * RP + row + a] = vs;
+        else
+          vsk[c] = pin(vs);
         vtk[c] = pin(vt);
         level_fence();
       }
@@ -445,7 +454,7 @@ __global__ __launch_bounds__((QPlane<Q>::THREADS), 2) void k_op_interp(
       __syncthreads();  // B and C have been read
 #pragma unroll
       for (int c = 0; c < Q; ++c) {
-        B[(c * Q) * RP + row + a] = vsk[c];
+        if constexpr (!PL::VS) B[(c * Q) * RP + row + a] = vsk[c];
         C[(c * Q) * RP + row + a] = x[c];
       }
       __syncthreads();
@@ -457,7 +466,7 @@ __global__ __launch_bounds__((QPlane<Q>::THREADS), 2) void k_op_interp(
         for (int m = 0; m < Q; ++m) {
           const int o = (c * Q) * RP + row + m;
           s0 += sD[m][ic] * A[o] + sJ[m][ic] * C[o];
-          s1 += sJ[m][ic] * B[o];
+          s1 += sJ[m][ic] * (PL::VS ? V[o] : B[o]);
         }
         vsk[c] = pin(s0);
         vtk[c] = pin(s1);

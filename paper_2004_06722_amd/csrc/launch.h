@@ -7,7 +7,10 @@ namespace bp {
 
 // operator kernels (ops.hip)
 bool kernels_cover(int p, int q, int quad);
-int64_t plane_epb(int p1, int q);
+int64_t plane_epb(int p1, int q, int which);
+// work-groups (= energy partial rows) of one operator launch for `which`;
+// apply_blocks is the largest over mass and stiffness (partial buffer size)
+int64_t apply_rows(const bp_op_s *op, int which);
 int64_t apply_blocks(const bp_op_s *op);
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s);
@@ -25,7 +28,7 @@ int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, dou
 constexpr int kVecThreads = 256;
 constexpr int64_t kVecMaxBlocks = 2048;
 constexpr int64_t kStage2Rows = 256;
-constexpr int64_t kDirectRows = 4096;
+constexpr int64_t kDirectRows = 16384;
 int64_t vec_blocks(int64_t n);
 int64_t grid_blocks(int64_t n);
 void fill_f64(double *x, int64_t n, double v, hipStream_t s);

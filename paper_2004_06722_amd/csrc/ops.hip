@@ -6,8 +6,11 @@
 
 namespace bp {
 
-int64_t plane_epb(int p1, int q) {
+// Elements per work-group of the operator kernel for (p1, q, which); the
+// Gauss-Legendre values mirror QPlane, the GLL ones Plane.
+int64_t plane_epb(int p1, int q, int which) {
   if (q > p1) {  // Gauss-Legendre kernels: q x q planes in up to 256 threads
+    if (which == BP_STIFF && (q == 8 || q == 10)) return q == 8 ? 3 : 1;
     const int n = q * q;
     return n >= 256 ? 1 : 256 / n;
   }
@@ -15,9 +18,14 @@ int64_t plane_epb(int p1, int q) {
   return n >= 64 ? 1 : 64 / n;
 }
 
-int64_t apply_blocks(const bp_op_s *op) {
-  const int64_t epb = plane_epb(op->p1, op->q);
+int64_t apply_rows(const bp_op_s *op, int which) {
+  const int64_t epb = plane_epb(op->p1, op->q, which);
   return (op->nelem + epb - 1) / epb;
+}
+
+int64_t apply_blocks(const bp_op_s *op) {
+  const int64_t a = apply_rows(op, BP_MASS), b = apply_rows(op, BP_STIFF);
+  return a > b ? a : b;
 }
 
 namespace {
@@ -46,10 +54,12 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
 template <int P1, int Q, typename T, bool STIFF>
 int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int masked,
            double *part, const int *done, hipStream_t s) {
-  using PL = QPlane<Q>;
+  using PL = QPlane<Q, STIFF>;
   static_assert(PL::EPB * Q * Q <= 256, "plane layout");
+  const int64_t grid = apply_rows(op, STIFF ? BP_STIFF : BP_MASS);
+  if (grid != (op->nelem + PL::EPB - 1) / PL::EPB) return set_error(BP_ERR_ARG, "plane layout");
   for (int c = 0; c < op->ncomp; ++c)
-    hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(apply_blocks(op)), dim3(PL::THREADS),
+    hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(grid), dim3(PL::THREADS),
                        0, s, op->nelem, op->idx, Gm, basis, u + c * op->nglobal,
                        w + c * op->nglobal, op->ncomp, c, masked, part, done);
   return BP_OK;

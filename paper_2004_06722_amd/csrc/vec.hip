@@ -16,31 +16,49 @@ namespace {
 
 constexpr int kFinThreads = 1024;
 
-// Fixed-order sum of `width` columns over nb rows: res[col] (shared).
-__device__ void reduce_columns(const double *__restrict__ part, int64_t nb, int width,
-                               double *res) {
-  __shared__ double sh[kFinThreads];
-  for (int col = 0; col < width; ++col) {
-    // rows t, t + 1024, ... in order; eight loads in flight per step
-    double s = 0.0;
-    int64_t r = threadIdx.x;
-    for (; r + 7 * kFinThreads < nb; r += 8 * kFinThreads) {
-      double v[8];
+// Fixed-order sum of W columns over nb rows into res[col] (shared): thread t
+// adds rows t, t + 1024, ... of every column in order (D loads in flight per
+// column), each wave folds its 64 lanes with a fixed shuffle tree, and the
+// first W threads add the 16 wave sums in order.
+template <int W>
+__device__ void reduce_columns(const double *__restrict__ part, int64_t nb, double *res) {
+  constexpr int NW = kFinThreads / 64;
+  constexpr int D = W <= 2 ? 8 : (W <= 6 ? 4 : 2);
+  __shared__ double wsum[NW][W];
+  double s[W];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = part[(r + q * kFinThreads) * width + col];
+  for (int c = 0; c < W; ++c) s[c] = 0.0;
+  int64_t r = threadIdx.x;
+  for (; r + (D - 1) * kFinThreads < nb; r += D * kFinThreads) {
+    double v[D][W];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += v[q];
-    }
-    for (; r < nb; r += kFinThreads) s += part[r * width + col];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = kFinThreads / 2; h > 0; h >>= 1) {
-      if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) res[col] = sh[0];
-    __syncthreads();
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) v[q][c] = part[(r + q * kFinThreads) * W + c];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) s[c] += v[q][c];
   }
+  for (; r < nb; r += kFinThreads)
+#pragma unroll
+    for (int c = 0; c < W; ++c) s[c] += part[r * W + c];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    double x = s[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) wsum[wid][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < W) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) x += wsum[k][threadIdx.x];
+    res[threadIdx.x] = x;
+  }
+  __syncthreads();
 }
 
 // Stage 1 of the fixed-order reduction: work-group b adds rows
@@ -140,10 +158,12 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_init(int64_t n, const T *__r
   block_partial1(bb, part, 3 * nc, 2 * nc + comp);
 }
 
+template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restrict__ part,
-                                                          int64_t nb, int nc, DevScalars *sc) {
-  __shared__ double res[3 * kMaxComp];
-  reduce_columns(part, nb, 3 * nc, res);
+                                                          int64_t nb, DevScalars *sc) {
+  constexpr int nc = NC;
+  __shared__ double res[3 * NC];
+  reduce_columns<3 * NC>(part, nb, res);
   if (threadIdx.x == 0) {
     int bad = 0;
     for (int c = 0; c < nc; ++c) {
@@ -161,14 +181,16 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restri
   }
 }
 
+template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restrict__ part,
-                                                           int64_t nb, int nc, DevScalars *sc) {
+                                                           int64_t nb, DevScalars *sc) {
+  constexpr int nc = NC;
   if (sc->done) {
     if (threadIdx.x == 0) sc->halted = 1;
     return;
   }
-  __shared__ double res[kMaxComp];
-  reduce_columns(part, nb, nc, res);
+  __shared__ double res[NC];
+  reduce_columns<NC>(part, nb, res);
   if (threadIdx.x == 0)
     for (int c = 0; c < nc; ++c) {
       const double pap = res[c];
@@ -204,11 +226,13 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
   block_partial1(rr, part, 2 * nc, nc + comp);
 }
 
+template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restrict__ part,
-                                                          int64_t nb, int nc, DevScalars *sc) {
+                                                          int64_t nb, DevScalars *sc) {
+  constexpr int nc = NC;
   if (sc->done) return;
-  __shared__ double res[2 * kMaxComp];
-  reduce_columns(part, nb, 2 * nc, res);
+  __shared__ double res[2 * NC];
+  reduce_columns<2 * NC>(part, nb, res);
   if (threadIdx.x == 0) {
     for (int c = 0; c < nc; ++c) {
       const double rz = res[c];
@@ -263,10 +287,12 @@ __global__ __launch_bounds__(kVecThreads) void k_dc_residual(int64_t n, const do
   block_partial1(bb, part, 2 * nc, nc + comp);
 }
 
+template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_norms(const double *__restrict__ part,
-                                                           int64_t nb, int nc, DevScalars *sc) {
-  __shared__ double res[2 * kMaxComp];
-  reduce_columns(part, nb, 2 * nc, res);
+                                                           int64_t nb, DevScalars *sc) {
+  constexpr int nc = NC;
+  __shared__ double res[2 * NC];
+  reduce_columns<2 * NC>(part, nb, res);
   if (threadIdx.x == 0)
     for (int c = 0; c < nc; ++c) {
       sc->rr[c] = res[c];
@@ -365,6 +391,42 @@ void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk3
                      G, kappa, Gk, Gk32, nelem, nq);
 }
 
+enum class FinKind { Init, Alpha, Beta, Norms };
+
+// the single-work-group finisher for nc components (compile-time widths)
+template <int NC>
+static void launch_fin_nc(FinKind k, const double *src, int64_t rows, DevScalars *sc,
+                          hipStream_t s) {
+  switch (k) {
+    case FinKind::Init:
+      hipLaunchKernelGGL(k_fin_init<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      break;
+    case FinKind::Alpha:
+      hipLaunchKernelGGL(k_fin_alpha<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      break;
+    case FinKind::Beta:
+      hipLaunchKernelGGL(k_fin_beta<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      break;
+    case FinKind::Norms:
+      hipLaunchKernelGGL(k_fin_norms<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      break;
+  }
+}
+
+static void launch_fin(FinKind k, int nc, const double *src, int64_t rows, DevScalars *sc,
+                       hipStream_t s) {
+  switch (nc) {
+    case 1: launch_fin_nc<1>(k, src, rows, sc, s); break;
+    case 2: launch_fin_nc<2>(k, src, rows, sc, s); break;
+    case 3: launch_fin_nc<3>(k, src, rows, sc, s); break;
+    case 4: launch_fin_nc<4>(k, src, rows, sc, s); break;
+    case 5: launch_fin_nc<5>(k, src, rows, sc, s); break;
+    case 6: launch_fin_nc<6>(k, src, rows, sc, s); break;
+    case 7: launch_fin_nc<7>(k, src, rows, sc, s); break;
+    default: launch_fin_nc<kMaxComp>(k, src, rows, sc, s); break;
+  }
+}
+
 template <typename T>
 void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, double *part,
              DevScalars *sc, hipStream_t s) {
@@ -373,13 +435,13 @@ void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, dou
                      part);
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, 3 * nc, part + nb * 3 * nc, &rows, s);
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
+  launch_fin(FinKind::Init, nc, src, rows, sc, s);
 }
 
 void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s) {
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, nc, const_cast<double *>(part) + nb * nc, &rows, s);
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
+  launch_fin(FinKind::Alpha, nc, src, rows, sc, s);
 }
 
 template <typename T>
@@ -393,7 +455,7 @@ void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStre
   int64_t rows = 0;
   const double *src =
       reduce_stage1(part, nb, 2 * nc, const_cast<double *>(part) + nb * 2 * nc, &rows, s);
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
+  launch_fin(FinKind::Beta, nc, src, rows, sc, s);
 }
 
 template <typename T>
@@ -409,7 +471,7 @@ void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, doubl
   hipLaunchKernelGGL(k_dc_residual, dim3(nb, nc), dim3(kVecThreads), 0, s, n, b, r, w, part);
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, 2 * nc, part + nb * 2 * nc, &rows, s);
-  hipLaunchKernelGGL(k_fin_norms, dim3(1), dim3(kFinThreads), 0, s, src, rows, nc, sc);
+  launch_fin(FinKind::Norms, nc, src, rows, sc, s);
 }
 
 void dc_accumulate(int64_t n, double *x, const float *d, hipStream_t s) {
