@@ -376,6 +376,62 @@ def workload_sweep13(args):
                         "100 fixed PCG iterations each, rhs uniform seed 0", "results": out}
 
 
+def workload_bk(args):
+    """The bake-off kernels on their own (bp_apply_local, w_L = A_L u_L with no
+    gather or scatter): E = 2^k elements, N from --sweep-n, per launch time,
+    TFLOP/s from the section 5 flop counts, bandwidth of G + u_L + w_L, and
+    time per point n_L = N^3 E with the 2x line of the single-GPU BK5 study
+    (section 8)."""
+    import numpy as np
+    import torch
+
+    from paper_2004_06722_amd import model
+    bp = args.bk
+    which = 3 if bp in (3, 4, 5, 6) else 1
+    curves = []
+    for N in args.sweep_n:
+        pts = []
+        for k in range(0, 19):
+            E = 2 ** k
+            if (N + 1) ** 3 * E > 1.5e8:
+                break
+            op, _, info = build_problem(bp, N, k)
+            nl_words = E * (N + 1) ** 3
+            uL = torch.from_numpy(np.random.default_rng(k).uniform(-1.0, 1.0, nl_words)).cuda()
+            w = torch.empty_like(uL)
+            for _ in range(3):
+                op.apply_local(which, uL, out=w)
+            reps = 20 if E >= 1024 else 200
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                op.apply_local(which, uL, out=w)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            op.close()
+            nl = N ** 3 * E
+            fl = model.apply_flops_per_element(bp, N) * E
+            by = model.local_apply_bytes(bp, N, E)
+            pts.append({"E": E, "n_L": nl, "ms": ms, "TFLOPs": fl / (ms * 1e-3) / 1e12,
+                        "GBs": by / (ms * 1e-3) / 1e9, "frac_hbm": by / (ms * 1e-3) / 1e9 /
+                        model.HBM_PEAK_GBS, "ns_per_point": ms * 1e6 / nl})
+        best = max(pts, key=lambda r: r["TFLOPs"])
+        log(f"BK{bp} N={N}: peak {best['TFLOPs']:.2f} TFLOP/s, {best['GBs']:.0f} GB/s "
+            f"({100 * best['frac_hbm']:.0f}% HBM) at E={best['E']}; "
+            f"min {min(r['ns_per_point'] for r in pts):.3f} ns/point")
+        curves.append({"N": N, "points": pts})
+    tmin = min(r["ns_per_point"] for c in curves for r in c["points"])
+    for c in curves:
+        # smallest n_L from which the time per point stays within 2x the minimum
+        ok = [r for r in c["points"] if r["ns_per_point"] <= 2 * tmin]
+        c["n_L_2x"] = min((r["n_L"] for r in ok), default=None)
+    return {"workload": f"BK{bp} alone (bp_apply_local), E = 2^k <= 2^18 with (N+1)^3 E <= 1.5e8, "
+                        "mean of 20-200 launches after 3 warm-up launches, u_L uniform[-1,1]",
+            "min_ns_per_point": tmin, "curves": curves}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,8 +449,10 @@ def main():
     ap.add_argument("--sweep-bp", type=int, nargs="+", default=[1, 3], help="sweep13: which BPs")
     ap.add_argument("--sweep-n", type=int, nargs="+", default=list(range(1, 9)),
                     help="sweep13: which orders N")
+    ap.add_argument("--bk", type=int, default=5, choices=[1, 3, 5],
+                    help="bk workload: which bake-off kernel")
     ap.add_argument("--workload", default="bp5",
-                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13"],
+                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13", "bk"],
                     help="bp5: the headline line; the others print their own record")
     args = ap.parse_args()
     if args.calib_copy:
@@ -404,7 +462,7 @@ def main():
         import torch
         torch.cuda.set_device(0)
         fn = {"vector": workload_vector, "mixed": workload_mixed, "adjoint": workload_adjoint,
-              "sweep13": workload_sweep13}[args.workload]
+              "sweep13": workload_sweep13, "bk": workload_bk}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:
@@ -440,7 +498,7 @@ def main():
     ab = model.apply_bytes(bp, N, E)
     achieved = ab / (apply_avg_ms * 1e-3) / 1e9
     it_bytes = model.iteration_bytes(bp, N, E)
-    kname = f"k_stiff_colloc<{N + 1}, double>"
+    kname = f"k_stiff_colloc<{N + 1}, double, false>"
     loop_s = st["ms"] * 1e-3
     result = {
         "metric": METRIC,

@@ -120,6 +120,23 @@ int bp_apply(bp_op op, int which, int prec, const void *u, void *w,
              unsigned flags, void *stream);
 
 /*
+ * bp_apply_local -- the bake-off kernels on their own: w_L = A_L u_L
+ * (BP_STIFF: BK3/BK5, and BK4/BK6 per component) or w_L = B_L u_L (BP_MASS:
+ * BK1/BK2), with A_L = block-diag(A^e) the unassembled operator of section 4
+ * and eq. (bk5x) / eq. (mass), evaluated element by element without the
+ * gather Q, the scatter Q^T or the Dirichlet mask (section 3, the BK
+ * definition; section 8, the single-GPU BK5 study).
+ *   uL, wL: device arrays [ncomp][nelem][(p+1)^3], local node id
+ *     i + p1 (j + p1 k); double for prec = BP_FP64, float for BP_FP32 (which
+ *     requires BP_SETUP_FP32). Every entry of wL is written; wL must not
+ *     alias uL. The κ of bp_set_coeff applies as in bp_apply.
+ * Errors: BP_ERR_ARG (which, prec, NULL or aliased vectors, or
+ * nelem (p+1)^3 >= 2^31), BP_ERR_HIP.
+ */
+int bp_apply_local(bp_op op, int which, int prec, const void *uL, void *wL,
+                   void *stream);
+
+/*
  * bp_diag -- d = diag(Q^T A_L Q) (or of B), the Jacobi preconditioner's
  * diagonal (section 3: diagonally preconditioned CG). d: device double
  * [nglobal] (the same for every component). With BP_MASKED, d = 0 on

@@ -48,6 +48,7 @@ SIGNATURES = {
     "bp_info": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_set_coeff": (_i, [_vp, _vp, _vp]),
     "bp_apply": (_i, [_vp, _i, _i, _vp, _vp, _u, _vp]),
+    "bp_apply_local": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "bp_diag": (_i, [_vp, _i, _vp, _u, _vp]),
     "bp_pcg_solve": (_i, [_vp, _i, _vp, _vp, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),
     "bp_pcg_solve_mixed": (_i, [_vp, _vp, _vp, _d, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),

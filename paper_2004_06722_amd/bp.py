@@ -119,6 +119,25 @@ class Operator:
                                  BP_MASKED if masked else 0, _stream()))
         return w
 
+    def apply_local(self, which: int, uL: torch.Tensor,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+        """w_L = A_L u_L or B_L u_L per element, no gather or scatter
+        (bp_apply_local). uL: [ncomp][nelem][(p+1)^3] (any shape with that many
+        contiguous entries); FP32 if uL is float32."""
+        prec = BP_FP32 if uL.dtype == torch.float32 else BP_FP64
+        nl = self.ncomp * self.nelem * (self.p + 1) ** 3
+        for t, name in ((uL, "uL"), (out, "out")):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+                raise TypeError(f"{name} must be a device tensor")
+            if t.dtype != uL.dtype or t.numel() != nl or not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous {uL.dtype} with "
+                                 "ncomp*nelem*(p+1)^3 entries")
+        w = torch.empty_like(uL) if out is None else out
+        check(self._lib.bp_apply_local(self._h, which, prec, _ptr(uL), _ptr(w), _stream()))
+        return w
+
     def diag(self, which: int, masked: bool = True) -> torch.Tensor:
         d = torch.empty(self.nglobal, dtype=torch.float64, device=self.device)
         check(self._lib.bp_diag(self._h, which, _ptr(d), BP_MASKED if masked else 0, _stream()))

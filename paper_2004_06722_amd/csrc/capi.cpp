@@ -437,6 +437,18 @@ int bp_apply(bp_op op, int which, int prec, const void *u, void *w, unsigned fla
                       nullptr, s);
 }
 
+int bp_apply_local(bp_op op, int which, int prec, const void *uL, void *wL, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_apply_local: which");
+  if (prec != BP_FP64 && prec != BP_FP32) return set_error(BP_ERR_ARG, "bp_apply_local: prec");
+  if (prec == BP_FP32 && !op->fp32)
+    return set_error(BP_ERR_ARG, "bp_apply_local: FP32 needs BP_SETUP_FP32");
+  if (!uL || !wL) return set_error(BP_ERR_ARG, "bp_apply_local: NULL vector");
+  if (uL == wL) return set_error(BP_ERR_ARG, "bp_apply_local: wL must not alias uL");
+  return launch_apply_local(op, which, prec == BP_FP32, uL, wL, (hipStream_t)stream);
+}
+
 int bp_diag(bp_op op, int which, double *d, unsigned flags, void *stream) {
   int rc = check_op(op);
   if (rc) return rc;

@@ -98,7 +98,7 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
 // accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
 // ---------------------------------------------------------------------------
-template <int P1, typename T>
+template <int P1, typename T, bool LOCAL = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *Dg,
     const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0, int masked,
@@ -128,7 +128,8 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
   int gk[P1];
   T g[6][P1];
 #pragma unroll
-  for (int k = 0; k < P1; ++k) gk[k] = __builtin_nontemporal_load(ie + k * PP);
+  for (int k = 0; k < P1; ++k)
+    gk[k] = LOCAL ? (int)(ec * N3) + ij + k * PP : __builtin_nontemporal_load(ie + k * PP);
 #pragma unroll
   for (int k = 0; k < P1; ++k)
 #pragma unroll
@@ -140,8 +141,8 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
     const int v = gk[k];
-    if (live && (v >= 0 || !masked)) mb |= 1u << k;
-    gk[k] = v >= 0 ? v : -1 - v;
+    if (live && (LOCAL || v >= 0 || !masked)) mb |= 1u << k;
+    if (!LOCAL) gk[k] = v >= 0 ? v : -1 - v;
   }
 
   // gather u (requested before D^ is staged, so both wait together)
@@ -215,7 +216,12 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
         acc += sDt[i][m] * sr[slot][c][k][j][m];
         acc += sDt[j][m] * ss[slot][c][k][m][i];
       }
-      if (mb >> k & 1u) atomic_add(w + gk[k], acc);
+      if (mb >> k & 1u) {
+        if constexpr (LOCAL)
+          w[gk[k]] = acc;  // element-local output: no assembly
+        else
+          atomic_add(w + gk[k], acc);
+      }
     }
   }
   if (part) block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0, 1);
@@ -225,7 +231,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 // Mass with collocated GLL quadrature: B_L is diagonal (section 5, remark
 // after eq. (mass)); w = Q^T (B~ .* Q u).
 // ---------------------------------------------------------------------------
-template <int P1, typename T>
+template <int P1, typename T, bool LOCAL = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Bt,
     const T *__restrict__ u, T *__restrict__ w, int64_t cstride, int ncomp, int masked,
@@ -243,8 +249,12 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
   T b[P1];
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
-    const int v = live ? idx[e * N3 + k * P1 * P1 + ij] : -1;
-    gk[k] = decode_index(v, live, masked);
+    if constexpr (LOCAL) {
+      gk[k] = live ? (int)(e * N3) + k * P1 * P1 + ij : -1;
+    } else {
+      const int v = live ? idx[e * N3 + k * P1 * P1 + ij] : -1;
+      gk[k] = decode_index(v, live, masked);
+    }
     b[k] = live ? Bt[e * N3 + k * P1 * P1 + ij] : T(0);
   }
   for (int cc = 0; cc < ncomp; ++cc) {
@@ -256,7 +266,10 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
       const T uv = u[o];
       const T wv = b[k] * uv;
       en[0] += (double)uv * (double)wv;
-      atomic_add(w + o, wv);
+      if constexpr (LOCAL)
+        w[o] = wv;
+      else
+        atomic_add(w + o, wv);
     }
     if (part) block_sum_store<1, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + cc, 1);
     __syncthreads();
@@ -310,7 +323,7 @@ struct QPlane {
   static constexpr int THREADS = ((USED + 63) / 64) * 64;
 };
 
-template <int P1, int Q, typename T, bool STIFF>
+template <int P1, int Q, typename T, bool STIFF, bool LOCAL = false>
 __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
     const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
@@ -352,7 +365,8 @@ __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
   // one round trip: node column of the gather map, quadrature column of G / B~
   int gk[P1];
 #pragma unroll
-  for (int k = 0; k < P1; ++k) gk[k] = idx[ec * N3 + ic + P1 * (jc + P1 * k)];
+  for (int k = 0; k < P1; ++k)
+    gk[k] = LOCAL ? (int)(ec * N3) + ic + P1 * (jc + P1 * k) : idx[ec * N3 + ic + P1 * (jc + P1 * k)];
   T g[NG][Q];
   const T *Ge = Gm + ec * NG * NQ + ab;
 #pragma unroll
@@ -364,8 +378,8 @@ __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
     const int v = gk[k];
-    if (live && a < P1 && b < P1 && (v >= 0 || !masked)) mb |= 1u << k;
-    gk[k] = v >= 0 ? v : -1 - v;
+    if (live && a < P1 && b < P1 && (LOCAL || v >= 0 || !masked)) mb |= 1u << k;
+    if (!LOCAL) gk[k] = v >= 0 ? v : -1 - v;
   }
   for (int x = t; x < Q * P1; x += PL::THREADS) {
     sJ[x / P1][x % P1] = basis[x];
@@ -526,7 +540,12 @@ __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
       T s = 0;
 #pragma unroll
       for (int c = 0; c < Q; ++c) s += Jg[c * P1 + k] * S[c];
-      if (mb >> k & 1u) atomic_add(w + gk[k], s);
+      if (mb >> k & 1u) {
+        if constexpr (LOCAL)
+          w[gk[k]] = s;  // element-local output: no assembly
+        else
+          atomic_add(w + gk[k], s);
+      }
     }
     double enb[1] = {en};
     if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + c0, 1);

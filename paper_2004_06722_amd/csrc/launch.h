@@ -14,6 +14,10 @@ int64_t apply_rows(const bp_op_s *op, int which);
 int64_t apply_blocks(const bp_op_s *op);
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s);
+// w_L = A_L u_L (or B_L u_L) per element, no gather or scatter; uL and wL are
+// [ncomp][nelem][p1^3] in the precision of f32
+int launch_apply_local(const bp_op_s *op, int which, bool f32, const void *uL, void *wL,
+                       hipStream_t s);
 int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_t s);
 int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, double *g,
                       hipStream_t s);

@@ -30,59 +30,69 @@ int64_t apply_blocks(const bp_op_s *op) {
 
 namespace {
 
-template <int P1, typename T>
+// Component stride of the vectors a launch reads and writes: global vectors
+// [ncomp][nglobal], or element-local vectors [ncomp][nelem][p1^3] (LOCAL).
+template <bool LOCAL>
+int64_t vec_stride(const bp_op_s *op) {
+  return LOCAL ? op->nelem * op->p1 * op->p1 * op->p1 : op->nglobal;
+}
+
+template <int P1, typename T, bool LOCAL>
 int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *u, T *w, int masked,
                  double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
   const T *Dg = basis + P1 * P1;  // D^ follows J^ (both p1 x p1 here)
+  const int64_t cs = vec_stride<LOCAL>(op);
   for (int c = 0; c < op->ncomp; ++c)
-    hipLaunchKernelGGL((k_stiff_colloc<P1, T>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
-                       op->nelem, op->idx, G, Dg, u + c * op->nglobal, w + c * op->nglobal,
-                       op->ncomp, c, masked, part, done);
+    hipLaunchKernelGGL((k_stiff_colloc<P1, T, LOCAL>), dim3(apply_blocks(op)), dim3(PL::THREADS),
+                       0, s, op->nelem, op->idx, G, Dg, u + c * cs, w + c * cs, op->ncomp, c,
+                       masked, part, done);
   return BP_OK;
 }
 
-template <int P1, typename T>
+template <int P1, typename T, bool LOCAL>
 int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, double *part,
                 const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
-  hipLaunchKernelGGL((k_mass_colloc<P1, T>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
-                     op->nelem, op->idx, Bt, u, w, op->nglobal, op->ncomp, masked, part, done);
+  hipLaunchKernelGGL((k_mass_colloc<P1, T, LOCAL>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0,
+                     s, op->nelem, op->idx, Bt, u, w, vec_stride<LOCAL>(op), op->ncomp, masked,
+                     part, done);
   return BP_OK;
 }
 
-template <int P1, int Q, typename T, bool STIFF>
+template <int P1, int Q, typename T, bool STIFF, bool LOCAL>
 int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int masked,
            double *part, const int *done, hipStream_t s) {
   using PL = QPlane<Q, STIFF>;
   static_assert(PL::EPB * Q * Q <= 256, "plane layout");
   const int64_t grid = apply_rows(op, STIFF ? BP_STIFF : BP_MASS);
   if (grid != (op->nelem + PL::EPB - 1) / PL::EPB) return set_error(BP_ERR_ARG, "plane layout");
+  const int64_t cs = vec_stride<LOCAL>(op);
   for (int c = 0; c < op->ncomp; ++c)
-    hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF>), dim3(grid), dim3(PL::THREADS),
-                       0, s, op->nelem, op->idx, Gm, basis, u + c * op->nglobal,
-                       w + c * op->nglobal, op->ncomp, c, masked, part, done);
+    hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF, LOCAL>), dim3(grid), dim3(PL::THREADS), 0,
+                       s, op->nelem, op->idx, Gm, basis, u + c * cs, w + c * cs, op->ncomp, c,
+                       masked, part, done);
   return BP_OK;
 }
 
-template <typename T>
+template <typename T, bool LOCAL>
 int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *basis, const T *u,
              T *w, int masked, double *part, const int *done, hipStream_t s) {
   const bool stiff = which == BP_STIFF;
   if (op->colloc) {
-#define BP_CASE(P)                                                                  \
-  case P:                                                                           \
-    return stiff ? stiff_colloc<P, T>(op, G, basis, u, w, masked, part, done, s)    \
-                 : mass_colloc<P, T>(op, Bt, u, w, masked, part, done, s);
+#define BP_CASE(P)                                                                         \
+  case P:                                                                                  \
+    return stiff ? stiff_colloc<P, T, LOCAL>(op, G, basis, u, w, masked, part, done, s)    \
+                 : mass_colloc<P, T, LOCAL>(op, Bt, u, w, masked, part, done, s);
     switch (op->p1) {
       BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
     }
 #undef BP_CASE
   } else if (op->q == op->p1 + 1) {
-#define BP_CASE(P)                                                                   \
-  case P:                                                                            \
-    return stiff ? interp<P, P + 1, T, true>(op, G, basis, u, w, masked, part, done, s) \
-                 : interp<P, P + 1, T, false>(op, Bt, basis, u, w, masked, part, done, s);
+#define BP_CASE(P)                                                                          \
+  case P:                                                                                   \
+    return stiff ? interp<P, P + 1, T, true, LOCAL>(op, G, basis, u, w, masked, part, done, s) \
+                 : interp<P, P + 1, T, false, LOCAL>(op, Bt, basis, u, w, masked, part, done, s);
     switch (op->p1) {
       BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
     }
@@ -107,8 +117,9 @@ bool kernels_cover(int p, int q, int quad) {
   return q == p + 2;
 }
 
-int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
-                 double *part, const int *done, hipStream_t s) {
+template <bool LOCAL>
+static int launch_apply_impl(const bp_op_s *op, int which, bool f32, const void *u, void *w,
+                             bool masked, double *part, const int *done, hipStream_t s) {
   int rc;
   // work-group size: 256 for the Gauss-Legendre planes, whole waves of p1^2 else
   const int64_t tpb = op->q > op->p1 ? 256 : ((op->p1 * op->p1 + 63) / 64) * 64;
@@ -116,16 +127,28 @@ int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w,
     return set_error(BP_ERR_ARG, "mesh too large for one operator launch (work-items >= 2^32)");
   if (f32) {
     const float *G = op->kappa_set ? op->Gk32 : op->G32;
-    rc = dispatch<float>(op, which, G, op->Bt32, op->basis32, (const float *)u, (float *)w,
-                         masked, part, done, s);
+    rc = dispatch<float, LOCAL>(op, which, G, op->Bt32, op->basis32, (const float *)u,
+                                (float *)w, masked, part, done, s);
   } else {
     const double *G = op->kappa_set ? op->Gk : op->G;
-    rc = dispatch<double>(op, which, G, op->Bt, op->basis_d, (const double *)u, (double *)w,
-                          masked, part, done, s);
+    rc = dispatch<double, LOCAL>(op, which, G, op->Bt, op->basis_d, (const double *)u,
+                                 (double *)w, masked, part, done, s);
   }
   if (rc != BP_OK) return rc;
   BP_HIP(hipGetLastError());
   return BP_OK;
+}
+
+int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
+                 double *part, const int *done, hipStream_t s) {
+  return launch_apply_impl<false>(op, which, f32, u, w, masked, part, done, s);
+}
+
+int launch_apply_local(const bp_op_s *op, int which, bool f32, const void *uL, void *wL,
+                       hipStream_t s) {
+  if (op->nelem * op->p1 * op->p1 * op->p1 >= (int64_t(1) << 31))
+    return set_error(BP_ERR_ARG, "bp_apply_local: nelem * (p+1)^3 must be below 2^31");
+  return launch_apply_impl<true>(op, which, f32, uL, wL, false, nullptr, nullptr, s);
 }
 
 int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_t s) {

@@ -36,6 +36,13 @@ def apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
         + word * VECTOR_WORDS_OPERATOR * n * ncomp
 
 
+def local_apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
+    """Bytes of one unassembled application w_L = A_L u_L (the BK kernels):
+    geometry + element-local u_L in + w_L out, (p+1)^3 words each per element
+    and component; no gather map."""
+    return E * (word * geometry_words(bp, p) + 2 * word * ncomp * (p + 1) ** 3)
+
+
 def iteration_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
     """Bytes of one CG iteration (operator + vector updates)."""
     n = p ** 3 * E
