@@ -3,7 +3,8 @@
 Section 4: A = Q^T A_L Q with A_L = blockdiag(A^e). Each element matrix is
 formed explicitly from Kronecker products of the 1D matrices (section 5:
 D1 = J^(x)J^(x)D^, D2 = J^(x)D^(x)J^, D3 = D^(x)J^(x)J^, J = J^(x)J^(x)J^),
-A^e = sum_mm' D_m^T diag(G_mm') D_m' and B^e = J^T diag(B~) J, then summed
+A^e = sum_mm' D_m^T diag(G_mm') D_m', B^e = J^T diag(B~) J and, for the Helmholtz
+operator of eq. (hm2), A^e + J^T diag(beta B~) J, then summed
 into a scipy.sparse matrix. This path shares nothing with the sum-factorised
 one in operators.py except the geometric factors.
 """
@@ -13,7 +14,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .geometry import G_PAIRS
-from .operators import MASS, STIFF, Discretization
+from .operators import HELM, MASS, STIFF, Discretization
 
 
 def kron_derivatives(rule):
@@ -31,10 +32,12 @@ def element_matrices(disc: Discretization, which: int, G=None) -> np.ndarray:
     Ds = (D1, D2, D3)
     n = disc.rule.p1 ** 3
     out = np.zeros((disc.E, n, n))
-    if which == MASS:
+    if which in (MASS, HELM):
+        Bt = disc.Bt if which == MASS else disc.beta * disc.Bt
         for e in range(disc.E):
-            out[e] = Jf.T @ (disc.Bt[e][:, None] * Jf)
-        return out
+            out[e] = Jf.T @ (Bt[e][:, None] * Jf)
+        if which == MASS:
+            return out
     G = disc.G_effective() if G is None else G
     for e in range(disc.E):
         for c, (m, mp) in enumerate(G_PAIRS):

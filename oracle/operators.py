@@ -5,6 +5,9 @@ Q^T its transpose (scatter-add) and A_L = blockdiag(A^e).
 Section 5, eq. (bk5x): A^e u^e = [D1;D2;D3]^T G^e [D1;D2;D3] u^e with
 D1 = J^(x)J^(x)D^, D2 = J^(x)D^(x)J^, D3 = D^(x)J^(x)J^.
 Section 5, eq. (mass): B^e u^e = J^T B~^e J u^e, J = J^(x)J^(x)J^.
+Section 4, eq. (hm2) with (ip1)-(ip2): the Helmholtz operator H = A + B_beta,
+where B_beta is the mass matrix with beta(x) at the quadrature points
+(B~ -> beta_q B~); HELM selects it.
 Appendix A1 (Nek5000 ax): Dirichlet values are removed by a mask after the
 assembly; "masked" here means w = mask * A (mask * u).
 
@@ -17,7 +20,7 @@ import numpy as np
 from .geometry import G_PAIRS, geometric_factors, tensor_apply, tensor_apply_t
 from .quadrature import Rule
 
-MASS, STIFF = 1, 3
+MASS, STIFF, HELM = 1, 3, 4
 
 
 class Discretization:
@@ -25,11 +28,12 @@ class Discretization:
 
     elem_dofs [E, p1^3] int, node_xyz [E, p1^3, 3], dirichlet [nglobal] flags
     or None (no Dirichlet nodes). kappa [E, q^3] scales G (variable mu of
-    eq. (hm1)); None means 1.
+    eq. (hm1)); None means 1. beta (a number or [E, q^3] values at the
+    quadrature points) is the beta of eq. (hm1) used by HELM; None means 0.
     """
 
     def __init__(self, rule: Rule, elem_dofs, node_xyz, nglobal: int,
-                 dirichlet=None, kappa=None):
+                 dirichlet=None, kappa=None, beta=None):
         self.rule = rule
         self.elem_dofs = np.asarray(elem_dofs, dtype=np.int64)
         self.E = self.elem_dofs.shape[0]
@@ -40,6 +44,11 @@ class Discretization:
         else:
             self.mask = 1.0 - np.asarray(dirichlet, dtype=np.float64)
         self.kappa = None if kappa is None else np.asarray(kappa, dtype=np.float64)
+        if beta is None:
+            self.beta = np.zeros((self.E, rule.q ** 3))
+        else:
+            self.beta = np.broadcast_to(np.asarray(beta, dtype=np.float64),
+                                        (self.E, rule.q ** 3)).copy()
 
     # -- Q and Q^T --------------------------------------------------------
     def gather(self, u):
@@ -78,25 +87,40 @@ class Discretization:
         return (tensor_apply_t(J, J, D, v[0]) + tensor_apply_t(J, D, J, v[1])
                 + tensor_apply_t(D, J, J, v[2]))
 
-    def mass_local(self, uL):
-        """w_L = B_L u_L = J^T B~ J u_L, eq. (mass)."""
+    def mass_local(self, uL, Bt=None):
+        """w_L = B_L u_L = J^T B~ J u_L, eq. (mass) (Bt replaces B~ if given)."""
         r = self.rule
         q = r.q
         J = r.J
         extra = uL.shape[4:]
-        Bq = self.Bt.reshape((self.E, q, q, q) + (1,) * len(extra))
+        Bt = self.Bt if Bt is None else Bt
+        Bq = Bt.reshape((self.E, q, q, q) + (1,) * len(extra))
         return tensor_apply_t(J, J, J, Bq * tensor_apply(J, J, J, uL))
+
+    def helm_local(self, uL):
+        """w_L = (A_L + B_beta,L) u_L: eq. (hm2), the stiffness of eq. (bk5x)
+        plus the mass of eq. (mass) with beta_q B~ at the points."""
+        return self.stiff_local(uL) + self.mass_local(uL, self.beta * self.Bt)
+
+    def local(self, which: int, uL):
+        if which == STIFF:
+            return self.stiff_local(uL)
+        if which == MASS:
+            return self.mass_local(uL)
+        if which == HELM:
+            return self.helm_local(uL)
+        raise ValueError("which must be MASS, STIFF or HELM")
 
     # -- assembled operators ----------------------------------------------
     def apply(self, which: int, u, masked: bool = True):
-        """w = [mask] Q^T A_L Q [mask] u for which in {MASS, STIFF}."""
+        """w = [mask] Q^T A_L Q [mask] u for which in {MASS, STIFF, HELM}."""
         u = np.asarray(u, dtype=np.float64)
         mshape = (self.nglobal,) + (1,) * (u.ndim - 1)
         m = self.mask.reshape(mshape)
         if masked:
             u = u * m
         uL = self.gather(u)
-        wL = self.stiff_local(uL) if which == STIFF else self.mass_local(uL)
+        wL = self.local(which, uL)
         w = self.scatter(wL, u.shape[1:])
         if masked:
             w = w * m
@@ -111,6 +135,13 @@ class Discretization:
         phi_3 = J^[a,i] J^[b,j] D^[c,k]. Mass: sum_abc B~ J^[a,i]^2 J^[b,j]^2 J^[c,k]^2.
         Masked: Dirichlet rows are set to 0.
         """
+        if which == HELM:
+            d = self.diag(STIFF, masked)
+            saved, self.Bt = self.Bt, self.beta * self.Bt
+            try:
+                return d + self.diag(MASS, masked)
+            finally:
+                self.Bt = saved
         r = self.rule
         q, p1 = r.q, r.p1
         J, D = r.J, r.D

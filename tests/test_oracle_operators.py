@@ -6,7 +6,7 @@ import scipy.sparse as sp
 import synth
 from oracle.assembled import assemble
 from oracle.geometry import geometric_factors, quad_weights3
-from oracle.operators import MASS, STIFF
+from oracle.operators import HELM, MASS, STIFF
 from oracle.quadrature import Rule, bp_rule
 from tests.oracle_cases import custom_disc, make_disc, rel_err
 
@@ -188,3 +188,46 @@ def test_sampled_apply_equals_full_apply():
     w = apply_at_nodes(disc.rule, mesh.elem_dofs[els], xyz, u, nodes, STIFF, True,
                        mesh.boundary)
     assert rel_err(w, full[nodes]) < 1e-14
+
+
+# -- Helmholtz operator, eq. (hm2): H = A + B_beta -------------------------------
+
+@pytest.mark.parametrize("p,quad", [(1, "gll"), (3, "gl"), (4, "gll"), (2, "gl")])
+def test_helmholtz_equals_brute_force(p, quad):
+    q = p + 2 if quad == "gl" else p + 1
+    rng = np.random.default_rng(20 + p)
+    beta_q = rng.uniform(0.5, 3.0, size=(2 * 2 * 2, q ** 3))
+    for beta in (0.7, beta_q):
+        disc, _ = custom_disc(p, q, quad, 2, 2, 2, seed=21, dirichlet=True, beta=beta)
+        for masked in (False, True):
+            H = assemble(disc, HELM, masked=masked)
+            u = rng.standard_normal(disc.nglobal)
+            assert rel_err(disc.apply(HELM, u, masked=masked), H @ u) < 1e-13
+            assert np.allclose(disc.diag(HELM, masked=masked), H.diagonal(),
+                               rtol=1e-13, atol=1e-15 * abs(H.diagonal()).max())
+
+
+@pytest.mark.parametrize("bp,p", [(5, 3), (3, 4), (5, 6)])
+def test_helmholtz_constant_integrates_beta(bp, p):
+    # A 1 = 0, so 1^T H 1 = int beta dx: beta times the volume (1) for a
+    # constant beta, and the quadrature sum of beta_q J_q w_q for a field
+    disc, mesh = make_disc(bp, p, 2, 3, 2, seed=22, dirichlet=False, beta=2.5)
+    one = np.ones(disc.nglobal)
+    assert abs(one @ disc.apply(HELM, one, masked=False) - 2.5) < 1e-12
+    q = disc.rule.q
+    xq = np.random.default_rng(23).uniform(0.2, 1.8, size=(disc.E, q ** 3))
+    disc_v, _ = make_disc(bp, p, 2, 3, 2, seed=22, dirichlet=False, beta=xq)
+    rho = disc.rule.rho
+    w3 = np.einsum("a,b,c->cba", rho, rho, rho).reshape(-1)
+    integral = np.sum(xq * disc.jac * w3[None, :])
+    assert abs(one @ disc_v.apply(HELM, one, masked=False) - integral) < 1e-12 * integral
+
+
+def test_helmholtz_with_zero_beta_is_stiffness_and_is_spd_without_dirichlet():
+    disc, _ = make_disc(5, 3, 2, 2, 2, seed=24, dirichlet=False)
+    u = np.random.default_rng(25).standard_normal(disc.nglobal)
+    assert rel_err(disc.apply(HELM, u), disc.apply(STIFF, u)) == 0.0
+    disc_b, _ = make_disc(5, 3, 2, 2, 2, seed=24, dirichlet=False, beta=1.0)
+    H = assemble(disc_b, HELM, masked=False).toarray()
+    assert np.allclose(H, H.T, atol=1e-13 * abs(H).max())
+    assert np.linalg.eigvalsh(H).min() > 0
