@@ -498,7 +498,7 @@ def main():
     ab = model.apply_bytes(bp, N, E)
     achieved = ab / (apply_avg_ms * 1e-3) / 1e9
     it_bytes = model.iteration_bytes(bp, N, E)
-    kname = f"k_stiff_colloc<{N + 1}, double, false>"
+    kname = f"k_stiff_colloc<{N + 1}, double, false, false>"
     loop_s = st["ms"] * 1e-3
     result = {
         "metric": METRIC,

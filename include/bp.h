@@ -47,7 +47,7 @@ enum bp_status {
 };
 
 enum bp_quad { BP_QUAD_GL = 0, BP_QUAD_GLL = 1 };
-enum bp_which { BP_MASS = 1, BP_STIFF = 3 };
+enum bp_which { BP_MASS = 1, BP_STIFF = 3, BP_HELM = 4 };
 enum bp_prec { BP_FP64 = 0, BP_FP32 = 1 };
 
 /* flags of bp_apply / bp_diag */
@@ -108,7 +108,24 @@ int bp_info(bp_op op, int64_t *nelem, int64_t *nglobal, int *p, int *q, int *nco
 int bp_set_coeff(bp_op op, const double *kappa_q, void *stream);
 
 /*
- * bp_apply -- w = Q^T A_L Q u (BP_STIFF) or Q^T B_L Q u (BP_MASS).
+ * bp_set_helmholtz -- beta of the Helmholtz operator H = A + B_beta used by
+ * which = BP_HELM (bp_apply, bp_apply_local, bp_diag, bp_pcg_solve).
+ * Section 4, eq. (hm1)-(hm2) with (ip1)-(ip2): -div(mu grad u) + beta u, where
+ * (v, u)_beta integrates beta v u; B_beta is the mass matrix of eq. (mass)
+ * with beta_q B~_q at the quadrature points. mu is the kappa of
+ * bp_set_coeff (1 by default).
+ *   beta_q: device double [nelem][q^3] (beta at the quadrature points, read
+ *     during the call), or NULL for the constant `beta`.
+ *   beta = 0 with beta_q = NULL removes the term (BP_HELM then equals
+ *   BP_STIFF). With GLL quadrature the term is fused into the stiffness kernel
+ *   (B_beta is diagonal); with GL points it is a second kernel adding into w.
+ * Errors: BP_ERR_ARG (non-finite beta), BP_ERR_OOM, BP_ERR_HIP.
+ */
+int bp_set_helmholtz(bp_op op, double beta, const double *beta_q, void *stream);
+
+/*
+ * bp_apply -- w = Q^T A_L Q u (BP_STIFF), Q^T B_L Q u (BP_MASS) or
+ * Q^T (A_L + B_beta,L) Q u (BP_HELM, see bp_set_helmholtz).
  * Section 4 (w = Q^T A_L Q u), section 5 eq. (bk5x) / eq. (mass); with
  * BP_MASKED, w = mask * A (mask * u) as the Dirichlet restriction of
  * Appendix A1 (Nek5000 ax).

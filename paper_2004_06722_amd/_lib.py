@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbp.so")
 BP_OK, BP_ERR_ARG, BP_ERR_MESH, BP_ERR_HIP = 0, -1, -2, -3
 BP_ERR_NONFINITE, BP_ERR_BREAKDOWN, BP_ERR_OOM = -4, -5, -6
 BP_QUAD_GL, BP_QUAD_GLL = 0, 1
-BP_MASS, BP_STIFF = 1, 3
+BP_MASS, BP_STIFF, BP_HELM = 1, 3, 4
 BP_FP64, BP_FP32 = 0, 1
 BP_MASKED = 1
 BP_SETUP_FP32 = 1
@@ -47,6 +47,7 @@ SIGNATURES = {
     "bp_setup": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _i64, _i64, _vp, _vp, _vp, _u, _vp]),
     "bp_info": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_set_coeff": (_i, [_vp, _vp, _vp]),
+    "bp_set_helmholtz": (_i, [_vp, ctypes.c_double, _vp, _vp]),
     "bp_apply": (_i, [_vp, _i, _i, _vp, _vp, _u, _vp]),
     "bp_apply_local": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "bp_diag": (_i, [_vp, _i, _vp, _u, _vp]),

@@ -12,10 +12,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (BP_FP32, BP_FP64, BP_MASKED, BP_MASS, BP_QUAD_GL, BP_QUAD_GLL,
+from ._lib import (BP_FP32, BP_FP64, BP_HELM, BP_MASKED, BP_MASS, BP_QUAD_GL, BP_QUAD_GLL,
                    BP_SETUP_FP32, BP_STIFF, PcgStats, check)
 
-MASS, STIFF = BP_MASS, BP_STIFF
+MASS, STIFF, HELM = BP_MASS, BP_STIFF, BP_HELM
 GL, GLL = BP_QUAD_GL, BP_QUAD_GLL
 
 
@@ -152,6 +152,15 @@ class Operator:
                     kappa.numel() != self.nelem * self.q ** 3 or not kappa.is_contiguous():
                 raise ValueError("kappa must be a contiguous float64 device tensor [nelem, q^3]")
         check(self._lib.bp_set_coeff(self._h, _ptr(kappa), _stream()))
+
+    def set_helmholtz(self, beta: float = 0.0, beta_q: torch.Tensor | None = None):
+        """beta of H = A + B_beta for which=HELM (bp_set_helmholtz): a constant,
+        or beta_q [nelem, q^3] at the quadrature points."""
+        if beta_q is not None:
+            if beta_q.dtype != torch.float64 or beta_q.device.type != "cuda" or \
+                    beta_q.numel() != self.nelem * self.q ** 3 or not beta_q.is_contiguous():
+                raise ValueError("beta_q must be a contiguous float64 device tensor [nelem, q^3]")
+        check(self._lib.bp_set_helmholtz(self._h, float(beta), _ptr(beta_q), _stream()))
 
     def pcg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, which: int = STIFF,
                   rtol: float = 1e-8, maxit: int = 1000, fixed_iters: bool = False):

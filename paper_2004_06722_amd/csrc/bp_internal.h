@@ -76,10 +76,12 @@ struct bp_op_s {
   double *Gk = nullptr;      // kappa_q * G (allocated by bp_set_coeff)
   double *Bt = nullptr;      // [E][q^3]
   double *basis_d = nullptr; // J | D | Dq on the device (FP64)
-  float *G32 = nullptr, *Gk32 = nullptr, *Bt32 = nullptr, *basis32 = nullptr;
+  double *Bb = nullptr;      // beta_q * B~ (allocated by bp_set_helmholtz; NULL: beta = 0)
+  float *G32 = nullptr, *Gk32 = nullptr, *Bt32 = nullptr, *Bb32 = nullptr, *basis32 = nullptr;
   bool kappa_set = false;
-  double *dinv[2] = {nullptr, nullptr};  // [0] mass, [1] stiffness (masked)
-  bool dinv_valid[2] = {false, false};
+  // inverse diagonals: [0] mass, [1] stiffness (masked), [2] Helmholtz (masked)
+  double *dinv[3] = {nullptr, nullptr, nullptr};
+  bool dinv_valid[3] = {false, false, false};
   // CG workspace
   double *r = nullptr, *pv = nullptr, *w = nullptr, *part = nullptr, *tmp = nullptr;
   float *r32 = nullptr, *p32 = nullptr, *w32 = nullptr, *x32 = nullptr, *b32 = nullptr;

@@ -54,8 +54,11 @@ void release(bp_op op) {
   dfree(op->Gk32);
   dfree(op->Bt32);
   dfree(op->basis32);
+  dfree(op->Bb);
+  dfree(op->Bb32);
   dfree(op->dinv[0]);
   dfree(op->dinv[1]);
+  dfree(op->dinv[2]);
   dfree(op->r);
   dfree(op->pv);
   dfree(op->w);
@@ -115,8 +118,12 @@ int check_op(bp_op op) {
 }
 
 // Inverse diagonal for `which` (cached; masked when the operator has Dirichlet nodes).
+int dinv_slot(int which) { return which == BP_STIFF ? 1 : (which == BP_HELM ? 2 : 0); }
+
+bool valid_which(int which) { return which == BP_MASS || which == BP_STIFF || which == BP_HELM; }
+
 int ensure_dinv(bp_op op, int which, hipStream_t s) {
-  const int slot = which == BP_STIFF ? 1 : 0;
+  const int slot = dinv_slot(which);
   if (op->dinv_valid[slot]) return BP_OK;
   if (!op->dinv[slot]) {
     int rc = dmalloc(&op->dinv[slot], op->nglobal);
@@ -353,7 +360,7 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRY(dmalloc(&op->tmp, std::max<int64_t>(nv, nglobal)));
   // partial sums of the largest grid, followed by the stage-1 rows
   op->part_len =
-      std::max<int64_t>(apply_blocks(op) * ncomp, vec_blocks(nglobal) * 3 * ncomp) +
+      std::max<int64_t>(max_partial_rows(op) * ncomp, vec_blocks(nglobal) * 3 * ncomp) +
       kStage2Rows * 3 * ncomp;
   TRY(dmalloc(&op->part, op->part_len));
   TRY(dmalloc(&op->sc, 1));
@@ -412,7 +419,35 @@ int bp_set_coeff(bp_op op, const double *kappa_q, void *stream) {
     BP_HIP(hipGetLastError());
     op->kappa_set = true;
   }
-  op->dinv_valid[1] = false;
+  op->dinv_valid[1] = op->dinv_valid[2] = false;
+  return BP_OK;
+}
+
+int bp_set_helmholtz(bp_op op, double beta, const double *beta_q, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!std::isfinite(beta)) return set_error(BP_ERR_ARG, "bp_set_helmholtz: beta must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t count = op->nelem * op->q * op->q * op->q;
+  if (!beta_q && beta == 0.0) {
+    // no beta term: free the scaled mass factors (BP_HELM = BP_STIFF)
+    BP_HIP(hipStreamSynchronize(s));
+    dfree(op->Bb);
+    dfree(op->Bb32);
+  } else {
+    if (!op->Bb) {
+      rc = dmalloc(&op->Bb, count);
+      if (rc) return rc;
+      if (op->fp32) {
+        rc = dmalloc(&op->Bb32, count);
+        if (rc) return rc;
+      }
+    }
+    scale_mass(op->Bt, beta_q, beta, op->Bb, op->Bb32, count, s);
+    BP_HIP(hipGetLastError());
+  }
+  // (the partial-sum buffer is sized at setup for both GL launches of BP_HELM)
+  op->dinv_valid[2] = false;
   return BP_OK;
 }
 
@@ -420,7 +455,7 @@ int bp_apply(bp_op op, int which, int prec, const void *u, void *w, unsigned fla
              void *stream) {
   int rc = check_op(op);
   if (rc) return rc;
-  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_apply: which");
+  if (!valid_which(which)) return set_error(BP_ERR_ARG, "bp_apply: which");
   if (prec != BP_FP64 && prec != BP_FP32) return set_error(BP_ERR_ARG, "bp_apply: prec");
   if (prec == BP_FP32 && !op->fp32)
     return set_error(BP_ERR_ARG, "bp_apply: FP32 needs BP_SETUP_FP32");
@@ -440,7 +475,7 @@ int bp_apply(bp_op op, int which, int prec, const void *u, void *w, unsigned fla
 int bp_apply_local(bp_op op, int which, int prec, const void *uL, void *wL, void *stream) {
   int rc = check_op(op);
   if (rc) return rc;
-  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_apply_local: which");
+  if (!valid_which(which)) return set_error(BP_ERR_ARG, "bp_apply_local: which");
   if (prec != BP_FP64 && prec != BP_FP32) return set_error(BP_ERR_ARG, "bp_apply_local: prec");
   if (prec == BP_FP32 && !op->fp32)
     return set_error(BP_ERR_ARG, "bp_apply_local: FP32 needs BP_SETUP_FP32");
@@ -452,7 +487,7 @@ int bp_apply_local(bp_op op, int which, int prec, const void *uL, void *wL, void
 int bp_diag(bp_op op, int which, double *d, unsigned flags, void *stream) {
   int rc = check_op(op);
   if (rc) return rc;
-  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_diag: which");
+  if (!valid_which(which)) return set_error(BP_ERR_ARG, "bp_diag: which");
   if (!d) return set_error(BP_ERR_ARG, "bp_diag: NULL output");
   if (flags & ~BP_MASKED) return set_error(BP_ERR_ARG, "bp_diag: unknown flag");
   hipStream_t s = (hipStream_t)stream;
@@ -464,7 +499,7 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
                  int fixed_iters, bp_pcg_stats *st, void *stream) {
   int rc = check_op(op);
   if (rc) return rc;
-  if (which != BP_MASS && which != BP_STIFF) return set_error(BP_ERR_ARG, "bp_pcg_solve: which");
+  if (!valid_which(which)) return set_error(BP_ERR_ARG, "bp_pcg_solve: which");
   if (!b || !x) return set_error(BP_ERR_ARG, "bp_pcg_solve: NULL vector");
   if (maxit < 0 || !(rtol >= 0.0)) return set_error(BP_ERR_ARG, "bp_pcg_solve: maxit/rtol");
   hipStream_t s = (hipStream_t)stream;
@@ -474,7 +509,7 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
   float ms = 0.0f;
   double apply_ms = 0.0;
   int apply_count = 0;
-  rc = pcg_run<double>(op, which, false, b, x, op->dinv[which == BP_STIFF ? 1 : 0], op->r, op->pv,
+  rc = pcg_run<double>(op, which, false, b, x, op->dinv[dinv_slot(which)], op->r, op->pv,
                        op->w, rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
                        &apply_count);
   if (st) {

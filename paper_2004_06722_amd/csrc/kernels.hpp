@@ -97,12 +97,15 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // are scalar loads from Dg (global memory, D^[a][m] at a * p1 + m); the
 // lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
 // accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
+// HELM adds the Helmholtz term of eq. (hm2): with collocated GLL points the
+// mass matrix is diagonal, so w_L += (beta B~) u_L node by node, with the
+// beta-scaled B~ read beside G (one more word per point).
 // ---------------------------------------------------------------------------
-template <int P1, typename T, bool LOCAL = false>
+template <int P1, typename T, bool LOCAL = false, bool HELM = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *Dg,
-    const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0, int masked,
-    double *__restrict__ part, const int *__restrict__ done) {
+    const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
+    int masked, double *__restrict__ part, const int *__restrict__ done) {
   constexpr int NC = 1;  // one component per launch; G is re-read per component
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
@@ -134,6 +137,12 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
   for (int k = 0; k < P1; ++k)
 #pragma unroll
     for (int n = 0; n < 6; ++n) g[n][k] = __builtin_nontemporal_load(Ge + n * N3 + k * PP);
+  // Helmholtz: beta B~ at the lane's nodes (B_beta is diagonal with GLL)
+  T bb[HELM ? P1 : 1];
+  if constexpr (HELM) {
+#pragma unroll
+    for (int k = 0; k < P1; ++k) bb[k] = __builtin_nontemporal_load(Bb + ec * N3 + ij + k * PP);
+  }
 
   // decode: global id, and bit k of mb set when node k is gathered and
   // scattered (clear for dead slots and masked Dirichlet nodes)
@@ -178,6 +187,11 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
   double en[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) en[c] = 0.0;
+  if constexpr (HELM) {
+    if (act)
+#pragma unroll
+      for (int k = 0; k < P1; ++k) en[0] += (double)ru[0][k] * (double)(bb[k] * ru[0][k]);
+  }
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
 #pragma unroll
@@ -210,6 +224,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T acc = 0;
+      if constexpr (HELM) acc = bb[k] * su[slot][c][k][j][i];
 #pragma unroll
       for (int m = 0; m < P1; ++m) {
         acc += Dg[m * P1 + k] * rt[c][m];

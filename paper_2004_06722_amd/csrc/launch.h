@@ -12,6 +12,8 @@ int64_t plane_epb(int p1, int q, int which);
 // apply_blocks is the largest over mass and stiffness (partial buffer size)
 int64_t apply_rows(const bp_op_s *op, int which);
 int64_t apply_blocks(const bp_op_s *op);
+// partial rows that any one operator application may write (buffer sizing)
+int64_t max_partial_rows(const bp_op_s *op);
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s);
 // w_L = A_L u_L (or B_L u_L) per element, no gather or scatter; uL and wL are
@@ -39,6 +41,9 @@ void fill_f64(double *x, int64_t n, double v, hipStream_t s);
 void fill_f32(float *x, int64_t n, float v, hipStream_t s);
 void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,
                     int64_t nelem, int nq, hipStream_t s);
+// Bb = beta_q * Bt (beta_q NULL: the constant beta), and its FP32 copy if Bb32
+void scale_mass(const double *Bt, const double *beta_q, double beta, double *Bb, float *Bb32,
+                int64_t count, hipStream_t s);
 void to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStream_t s);
 

@@ -19,6 +19,11 @@ int64_t plane_epb(int p1, int q, int which) {
 }
 
 int64_t apply_rows(const bp_op_s *op, int which) {
+  if (which == BP_HELM) {
+    // GL: the stiffness launch, then the beta-mass launch writes its rows
+    const int64_t st = apply_rows(op, BP_STIFF);
+    return op->colloc || !op->Bb ? st : st + apply_rows(op, BP_MASS);
+  }
   const int64_t epb = plane_epb(op->p1, op->q, which);
   return (op->nelem + epb - 1) / epb;
 }
@@ -26,6 +31,10 @@ int64_t apply_rows(const bp_op_s *op, int which) {
 int64_t apply_blocks(const bp_op_s *op) {
   const int64_t a = apply_rows(op, BP_MASS), b = apply_rows(op, BP_STIFF);
   return a > b ? a : b;
+}
+
+int64_t max_partial_rows(const bp_op_s *op) {
+  return apply_rows(op, BP_MASS) + apply_rows(op, BP_STIFF);
 }
 
 namespace {
@@ -37,16 +46,16 @@ int64_t vec_stride(const bp_op_s *op) {
   return LOCAL ? op->nelem * op->p1 * op->p1 * op->p1 : op->nglobal;
 }
 
-template <int P1, typename T, bool LOCAL>
-int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *u, T *w, int masked,
-                 double *part, const int *done, hipStream_t s) {
+template <int P1, typename T, bool LOCAL, bool HELM>
+int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *Bb, const T *u, T *w,
+                 int masked, double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
   const T *Dg = basis + P1 * P1;  // D^ follows J^ (both p1 x p1 here)
   const int64_t cs = vec_stride<LOCAL>(op);
   for (int c = 0; c < op->ncomp; ++c)
-    hipLaunchKernelGGL((k_stiff_colloc<P1, T, LOCAL>), dim3(apply_blocks(op)), dim3(PL::THREADS),
-                       0, s, op->nelem, op->idx, G, Dg, u + c * cs, w + c * cs, op->ncomp, c,
-                       masked, part, done);
+    hipLaunchKernelGGL((k_stiff_colloc<P1, T, LOCAL, HELM>), dim3(apply_blocks(op)),
+                       dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Dg, Bb, u + c * cs,
+                       w + c * cs, op->ncomp, c, masked, part, done);
   return BP_OK;
 }
 
@@ -75,24 +84,39 @@ int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int
   return BP_OK;
 }
 
+// which = BP_HELM: H = A + B_beta (eq. (hm2)). With GLL the beta term is fused
+// into the stiffness kernel; with GL points the mass kernel runs after the
+// stiffness kernel with beta B~ in place of B~, adding into the same w, and
+// writes its energy partials after the stiffness ones.
 template <typename T, bool LOCAL>
-int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *basis, const T *u,
-             T *w, int masked, double *part, const int *done, hipStream_t s) {
-  const bool stiff = which == BP_STIFF;
+int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *Bb,
+             const T *basis, const T *u, T *w, int masked, double *part, const int *done,
+             hipStream_t s) {
+  const bool stiff = which != BP_MASS;
+  const bool helm = which == BP_HELM && Bb != nullptr;
   if (op->colloc) {
-#define BP_CASE(P)                                                                         \
-  case P:                                                                                  \
-    return stiff ? stiff_colloc<P, T, LOCAL>(op, G, basis, u, w, masked, part, done, s)    \
-                 : mass_colloc<P, T, LOCAL>(op, Bt, u, w, masked, part, done, s);
+#define BP_CASE(P)                                                                        \
+  case P:                                                                                 \
+    if (!stiff) return mass_colloc<P, T, LOCAL>(op, Bt, u, w, masked, part, done, s);     \
+    return helm ? stiff_colloc<P, T, LOCAL, true>(op, G, basis, Bb, u, w, masked, part,   \
+                                                  done, s)                                \
+                : stiff_colloc<P, T, LOCAL, false>(op, G, basis, Bb, u, w, masked, part,  \
+                                                   done, s);
     switch (op->p1) {
       BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
     }
 #undef BP_CASE
   } else if (op->q == op->p1 + 1) {
-#define BP_CASE(P)                                                                          \
-  case P:                                                                                   \
-    return stiff ? interp<P, P + 1, T, true, LOCAL>(op, G, basis, u, w, masked, part, done, s) \
-                 : interp<P, P + 1, T, false, LOCAL>(op, Bt, basis, u, w, masked, part, done, s);
+    double *part2 = part ? part + apply_rows(op, BP_STIFF) * op->ncomp : nullptr;
+#define BP_CASE(P)                                                                             \
+  case P: {                                                                                    \
+    if (!stiff) return interp<P, P + 1, T, false, LOCAL>(op, Bt, basis, u, w, masked, part,   \
+                                                         done, s);                             \
+    int rc = interp<P, P + 1, T, true, LOCAL>(op, G, basis, u, w, masked, part, done, s);      \
+    if (rc == BP_OK && helm)                                                                   \
+      rc = interp<P, P + 1, T, false, LOCAL>(op, Bb, basis, u, w, masked, part2, done, s);     \
+    return rc;                                                                                 \
+  }
     switch (op->p1) {
       BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
     }
@@ -127,12 +151,12 @@ static int launch_apply_impl(const bp_op_s *op, int which, bool f32, const void 
     return set_error(BP_ERR_ARG, "mesh too large for one operator launch (work-items >= 2^32)");
   if (f32) {
     const float *G = op->kappa_set ? op->Gk32 : op->G32;
-    rc = dispatch<float, LOCAL>(op, which, G, op->Bt32, op->basis32, (const float *)u,
-                                (float *)w, masked, part, done, s);
+    rc = dispatch<float, LOCAL>(op, which, G, op->Bt32, op->Bb32, op->basis32,
+                                (const float *)u, (float *)w, masked, part, done, s);
   } else {
     const double *G = op->kappa_set ? op->Gk : op->G;
-    rc = dispatch<double, LOCAL>(op, which, G, op->Bt, op->basis_d, (const double *)u,
-                                 (double *)w, masked, part, done, s);
+    rc = dispatch<double, LOCAL>(op, which, G, op->Bt, op->Bb, op->basis_d,
+                                 (const double *)u, (double *)w, masked, part, done, s);
   }
   if (rc != BP_OK) return rc;
   BP_HIP(hipGetLastError());
@@ -156,12 +180,16 @@ int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_
   const size_t lds = sizeof(double) *
                      ((size_t)q * q * q + (size_t)q * q * p1 + (size_t)q * p1 * p1 +
                       (size_t)p1 * p1 * p1 + 2 * (size_t)q * p1);
-  const bool stiff = which == BP_STIFF;
-  const double *Gm = stiff ? (op->kappa_set ? op->Gk : op->G) : op->Bt;
   const int64_t grid = op->nelem < 65536 ? op->nelem : 65536;
-  hipLaunchKernelGGL(k_diag, dim3(grid), dim3(256), lds, s, op->nelem, p1, q, stiff ? 1 : 0,
-                     op->idx, Gm, op->basis_d, d, masked ? 1 : 0);
-  BP_HIP(hipGetLastError());
+  // BP_HELM: diag(A) + diag(B_beta), both added into d
+  const bool helm = which == BP_HELM && op->Bb != nullptr;
+  for (int part = 0; part < (helm ? 2 : 1); ++part) {
+    const bool stiff = part == 0 && which != BP_MASS;
+    const double *Gm = stiff ? (op->kappa_set ? op->Gk : op->G) : (part == 1 ? op->Bb : op->Bt);
+    hipLaunchKernelGGL(k_diag, dim3(grid), dim3(256), lds, s, op->nelem, p1, q, stiff ? 1 : 0,
+                       op->idx, Gm, op->basis_d, d, masked ? 1 : 0);
+    BP_HIP(hipGetLastError());
+  }
   return BP_OK;
 }
 

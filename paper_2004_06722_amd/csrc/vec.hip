@@ -343,6 +343,20 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_geometry(const double *__
   }
 }
 
+// Bb[i] = beta_i * Bt[i] with beta_i = beta_q[i], or beta if beta_q is NULL
+__global__ __launch_bounds__(kVecThreads) void k_scale_mass(const double *__restrict__ Bt,
+                                                            const double *__restrict__ beta_q,
+                                                            double beta, double *__restrict__ Bb,
+                                                            float *__restrict__ Bb32,
+                                                            int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * kVecThreads) {
+    const double v = (beta_q ? beta_q[i] : beta) * Bt[i];
+    Bb[i] = v;
+    if (Bb32) Bb32[i] = (float)v;
+  }
+}
+
 }  // namespace
 
 int64_t vec_blocks(int64_t n) {
@@ -425,6 +439,12 @@ static void launch_fin(FinKind k, int nc, const double *src, int64_t rows, DevSc
     case 7: launch_fin_nc<7>(k, src, rows, sc, s); break;
     default: launch_fin_nc<kMaxComp>(k, src, rows, sc, s); break;
   }
+}
+
+void scale_mass(const double *Bt, const double *beta_q, double beta, double *Bb, float *Bb32,
+                int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_mass, dim3(grid_blocks(count)), dim3(kVecThreads), 0, s, Bt, beta_q,
+                     beta, Bb, Bb32, count);
 }
 
 template <typename T>

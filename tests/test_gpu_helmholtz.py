@@ -1,0 +1,110 @@
+"""GPU parity of the Helmholtz operator H = A + B_beta (eq. (hm2)): apply,
+element-local apply, diagonal and Jacobi-PCG iterates against the oracle,
+for a constant beta and for beta given at the quadrature points, on GLL
+meshes (term fused into the stiffness kernel) and GL meshes (a second
+kernel adding into w). Meshes span several work-groups with a ragged last
+one; the bar is the FP64 normwise 1e-12."""
+import numpy as np
+import pytest
+
+from oracle.operators import HELM, STIFF, Discretization
+from oracle.pcg import pcg
+from tests.gpu_cases import TOL, Case, rel
+from tests.test_gpu_local import local_input, oracle_local, run_local
+from tests.test_gpu_parity import dev, host, host_array
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def helm_disc(c, beta):
+    return Discretization(c.disc.rule, c.mesh.elem_dofs, c.mesh.node_xyz, c.disc.nglobal,
+                          c.dir, beta=beta)
+
+
+def beta_field(c, seed):
+    return np.random.default_rng(seed).uniform(0.5, 3.0, size=(c.disc.E, c.q ** 3))
+
+
+def set_beta(c, beta):
+    if np.ndim(beta) == 0:
+        c.op.set_helmholtz(float(beta))
+    else:
+        c.op.set_helmholtz(0.0, torch.tensor(beta, device="cuda"))
+
+
+@pytest.mark.parametrize("bp,p", [(5, 1), (5, 3), (5, 6), (5, 7), (5, 8),
+                                  (3, 1), (3, 3), (3, 5), (3, 7), (3, 8)])
+def test_helmholtz_apply_matches_oracle(bp, p):
+    c = Case(bp, p, *((3, 3, 3) if p <= 4 else (3, 2, 2)), seed=60 + p)
+    try:
+        u = c.vec(61 + p)
+        for beta in (1.7, beta_field(c, 62 + p)):
+            set_beta(c, beta)
+            hd = helm_disc(c, beta)
+            for masked in (False, True):
+                w = host(c.op.apply(HELM, dev(u), masked=masked))
+                ref = hd.apply(HELM, u, masked=masked)
+                assert rel(w, ref) <= TOL, (masked, rel(w, ref))
+            d = host_array(c.op.diag(HELM))
+            assert rel(d, hd.diag(HELM)) <= TOL
+            uL = local_input(c, 63 + p)
+            assert rel(run_local(c.op, HELM, uL), oracle_local_helm(hd, uL)) <= TOL
+    finally:
+        c.close()
+
+
+def oracle_local_helm(disc, uL):
+    p1 = disc.rule.p1
+    x = np.moveaxis(uL, 0, -1).reshape((disc.E, p1, p1, p1, uL.shape[0]))
+    w = disc.helm_local(x)
+    return np.moveaxis(w.reshape(disc.E, p1 ** 3, uL.shape[0]), -1, 0)
+
+
+def test_zero_beta_is_stiffness_and_beta_can_be_reset():
+    c = Case(5, 4, 3, 3, 3, seed=70)
+    try:
+        u = dev(c.vec(71))
+        a = c.op.apply(STIFF, u)
+        torch.testing.assert_close(c.op.apply(HELM, u), a, rtol=0, atol=0)
+        c.op.set_helmholtz(2.0)
+        assert not torch.equal(c.op.apply(HELM, u), a)
+        c.op.set_helmholtz(0.0)
+        torch.testing.assert_close(c.op.apply(HELM, u), a, rtol=0, atol=0)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("bp,p,ncomp", [(5, 7, 1), (5, 3, 3), (3, 4, 1), (3, 7, 2)])
+def test_helmholtz_pcg_iterates_match_oracle(bp, p, ncomp):
+    c = Case(bp, p, *((3, 3, 3) if p <= 4 else (3, 2, 2)), seed=72, ncomp=ncomp)
+    try:
+        beta = beta_field(c, 73)
+        set_beta(c, beta)
+        hd = helm_disc(c, beta)
+        mask = 1 - c.mesh.boundary
+        b = c.vec(74) * (mask[:, None] if ncomp > 1 else mask)
+        rec = []
+        pcg(lambda v: hd.apply(HELM, v), b, hd.jacobi_inverse(HELM), maxit=8,
+            fixed_iters=True, record=rec)
+        for k in (1, 4, 8):
+            x, st = c.op.pcg_solve(dev(b), which=HELM, maxit=k, fixed_iters=True)
+            assert rel(host(x), rec[k - 1]) <= TOL, (k, rel(host(x), rec[k - 1]))
+    finally:
+        c.close()
+
+
+def test_helmholtz_without_dirichlet_converges():
+    # beta > 0 makes H definite without boundary conditions (BP1-type mesh)
+    c = Case(1, 5, 3, 2, 2, seed=75, dirichlet=False)
+    try:
+        c.op.set_helmholtz(4.0)
+        hd = helm_disc(c, 4.0)
+        b = c.vec(76)
+        x, st = c.op.pcg_solve(dev(b), which=HELM, rtol=1e-13, maxit=2000)
+        assert st["converged"]
+        ref, info = pcg(lambda v: hd.apply(HELM, v, masked=False), b,
+                        hd.jacobi_inverse(HELM, masked=False), rtol=1e-13, maxit=2000)
+        assert rel(host(x), ref) <= 1e-11
+    finally:
+        c.close()
