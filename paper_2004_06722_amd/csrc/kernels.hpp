@@ -307,7 +307,8 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
 // idle; the G (or B~) column and the gather map are requested at entry. The
 // local energy is accumulated at the quadrature points. One component per
 // launch (u and w point at component c0): keeping G live across a loop over
-// components would cost the registers that the later stages reuse.
+// components would cost the registers that the later stages reuse. With
+// LOCAL the result is stored per element (added to w when accum is set).
 // ---------------------------------------------------------------------------
 // Scheduling fence between the quadrature levels of a stage: without it the
 // scheduler issues the LDS reads of every level at once and the lane runs out
@@ -342,7 +343,7 @@ template <int P1, int Q, typename T, bool STIFF, bool LOCAL = false>
 __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
     const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
-    int masked, double *__restrict__ part, const int *__restrict__ done) {
+    int masked, int accum, double *__restrict__ part, const int *__restrict__ done) {
   using PL = QPlane<Q, STIFF>;
   constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QQ = Q * Q;
   constexpr int RP = Q + 1;       // tile row: q entries and one pad entry
@@ -556,8 +557,8 @@ __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
 #pragma unroll
       for (int c = 0; c < Q; ++c) s += Jg[c * P1 + k] * S[c];
       if (mb >> k & 1u) {
-        if constexpr (LOCAL)
-          w[gk[k]] = s;  // element-local output: no assembly
+        if constexpr (LOCAL)  // element-local output, one lane per entry: no assembly
+          w[gk[k]] = accum ? w[gk[k]] + s : s;
         else
           atomic_add(w + gk[k], s);
       }

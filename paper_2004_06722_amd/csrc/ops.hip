@@ -71,7 +71,7 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
 
 template <int P1, int Q, typename T, bool STIFF, bool LOCAL>
 int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int masked,
-           double *part, const int *done, hipStream_t s) {
+           double *part, const int *done, hipStream_t s, int accum = 0) {
   using PL = QPlane<Q, STIFF>;
   static_assert(PL::EPB * Q * Q <= 256, "plane layout");
   const int64_t grid = apply_rows(op, STIFF ? BP_STIFF : BP_MASS);
@@ -80,7 +80,7 @@ int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int
   for (int c = 0; c < op->ncomp; ++c)
     hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF, LOCAL>), dim3(grid), dim3(PL::THREADS), 0,
                        s, op->nelem, op->idx, Gm, basis, u + c * cs, w + c * cs, op->ncomp, c,
-                       masked, part, done);
+                       masked, accum, part, done);
   return BP_OK;
 }
 
@@ -114,7 +114,7 @@ int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *Bb,
                                                          done, s);                             \
     int rc = interp<P, P + 1, T, true, LOCAL>(op, G, basis, u, w, masked, part, done, s);      \
     if (rc == BP_OK && helm)                                                                   \
-      rc = interp<P, P + 1, T, false, LOCAL>(op, Bb, basis, u, w, masked, part2, done, s);     \
+      rc = interp<P, P + 1, T, false, LOCAL>(op, Bb, basis, u, w, masked, part2, done, s, 1);  \
     return rc;                                                                                 \
   }
     switch (op->p1) {
