@@ -62,15 +62,16 @@ def oracle_local_helm(disc, uL):
 
 
 def test_zero_beta_is_stiffness_and_beta_can_be_reset():
+    # same kernel both times; only the order of the atomic adds may differ
     c = Case(5, 4, 3, 3, 3, seed=70)
     try:
         u = dev(c.vec(71))
-        a = c.op.apply(STIFF, u)
-        torch.testing.assert_close(c.op.apply(HELM, u), a, rtol=0, atol=0)
+        a = host(c.op.apply(STIFF, u))
+        assert rel(host(c.op.apply(HELM, u)), a) <= 1e-15
         c.op.set_helmholtz(2.0)
-        assert not torch.equal(c.op.apply(HELM, u), a)
+        assert rel(host(c.op.apply(HELM, u)), a) > 1e-3
         c.op.set_helmholtz(0.0)
-        torch.testing.assert_close(c.op.apply(HELM, u), a, rtol=0, atol=0)
+        assert rel(host(c.op.apply(HELM, u)), a) <= 1e-15
     finally:
         c.close()
 
