@@ -165,8 +165,9 @@ def n08_from_sweep(points):
 # ---------------------------------------------------------------------------
 # secondary workloads (one JSON line each); the default run is the BP5 line
 # ---------------------------------------------------------------------------
-def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0):
-    """Fixed-iteration PCG on BPj; returns (record dict, operator kernel avg ms)."""
+def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0, helm_beta=None):
+    """Fixed-iteration PCG on BPj (or on H = A + beta B with helm_beta);
+    returns a record dict with the operator kernel average."""
     import torch
 
     from paper_2004_06722_amd import model
@@ -174,6 +175,9 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0):
     op, b, info = build_problem(bp, N, grid, ncomp=ncomp, seed=seed)
     op.set_option(BP_OPT_TIME_APPLY, 1)
     which = 1 if bp in (1, 2) else 3
+    if helm_beta is not None:
+        op.set_helmholtz(helm_beta)
+        which = 4
     if warmup:
         op.pcg_solve(b, which=which, maxit=warmup, fixed_iters=True)
     torch.cuda.synchronize()
@@ -185,8 +189,10 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0):
     E, n = info["E"], info["n"]
     log(f"BP{bp} N={N} E={E} ncomp={ncomp}: {steps} iterations in {wall * 1e3:.1f} ms")
     apply_ms = st["apply_ms"] / max(st["apply_count"], 1)
-    ab = model.apply_bytes(bp, N, E, ncomp)
-    return {"bp": bp, "N": N, "E": E, "ncomp": ncomp, "n": n, "n_unique": info["n_unique"],
+    ab = (model.apply_bytes(bp, N, E, ncomp) if helm_beta is None
+          else model.helm_apply_bytes(bp, N, E, ncomp))
+    return {"bp": bp, "helm_beta": helm_beta, "N": N, "E": E, "ncomp": ncomp, "n": n,
+            "n_unique": info["n_unique"],
             "iters": steps, "wall_ms": wall * 1e3, "ms_per_iter": wall * 1e3 / steps,
             "DOFs_per_s": steps * n * ncomp / wall,
             "apply_avg_ms": apply_ms, "apply_alg_GBs": ab / (apply_ms * 1e-3) / 1e9,
@@ -376,6 +382,22 @@ def workload_sweep13(args):
                         "100 fixed PCG iterations each, rhs uniform seed 0", "results": out}
 
 
+def workload_helmholtz(args):
+    """H = A + beta B (eq. (hm2), beta = 1) against the stiffness alone: BP5-type
+    (GLL, term fused into the kernel) at N=7, E=64^3 and BP3-type (GL, a second
+    kernel) at N=7, E=48^3; 100 fixed Jacobi-PCG iterations each."""
+    rows = []
+    for bp, grid in ((5, (64, 64, 64)), (3, (48, 48, 48))):
+        a = run_fixed(bp, 7, grid, 1)
+        h = run_fixed(bp, 7, grid, 1, helm_beta=1.0)
+        h["ratio_vs_stiffness"] = h["DOFs_per_s"] / a["DOFs_per_s"]
+        log(f"BP{bp}-type N=7: stiffness {a['DOFs_per_s']:.3e}, Helmholtz {h['DOFs_per_s']:.3e} "
+            f"DOFs/s (operator {a['apply_avg_ms']:.3f} vs {h['apply_avg_ms']:.3f} ms)")
+        rows += [a, h]
+    return {"workload": "Helmholtz H = A + B_beta (beta = 1) vs stiffness, N=7, 100 fixed PCG "
+                        "iterations, rhs uniform seed 0", "unit": "DOFs/s", "records": rows}
+
+
 def workload_bk(args):
     """The bake-off kernels on their own (bp_apply_local, w_L = A_L u_L with no
     gather or scatter): E = 2^k elements, N from --sweep-n, per launch time,
@@ -452,7 +474,7 @@ def main():
     ap.add_argument("--bk", type=int, default=5, choices=[1, 3, 5],
                     help="bk workload: which bake-off kernel")
     ap.add_argument("--workload", default="bp5",
-                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13", "bk"],
+                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13", "bk", "helmholtz"],
                     help="bp5: the headline line; the others print their own record")
     args = ap.parse_args()
     if args.calib_copy:
@@ -462,7 +484,8 @@ def main():
         import torch
         torch.cuda.set_device(0)
         fn = {"vector": workload_vector, "mixed": workload_mixed, "adjoint": workload_adjoint,
-              "sweep13": workload_sweep13, "bk": workload_bk}[args.workload]
+              "sweep13": workload_sweep13, "bk": workload_bk,
+              "helmholtz": workload_helmholtz}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:

@@ -36,6 +36,12 @@ def apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
         + word * VECTOR_WORDS_OPERATOR * n * ncomp
 
 
+def helm_apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
+    """Bytes of one Helmholtz application H = A + B_beta (eq. (hm2)) read once:
+    the stiffness application plus beta B~ (q^3 words per element)."""
+    return apply_bytes(bp, p, E, ncomp, word) + E * word * quadrature(bp, p) ** 3
+
+
 def local_apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
     """Bytes of one unassembled application w_L = A_L u_L (the BK kernels):
     geometry + element-local u_L in + w_L out, (p+1)^3 words each per element
