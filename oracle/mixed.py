@@ -6,6 +6,13 @@ the hot path: the outer loop forms the FP64 residual r = b - A x, stops when
 Jacobi-PCG whose operator, geometric factors and vectors are float32 (dot
 products accumulated in float64), and updates x += d in float64.
 The inner PCG is the same algorithm as pcg.pcg.
+
+reliable_cg is the second variant: one FP32 Jacobi-PCG whose search
+direction is kept for the whole solve, with the FP64 update x += x32 and the
+FP64 residual r = b - A x substituted for the recursive FP32 residual
+whenever the latter has dropped by the factor delta since the last
+substitution ("reliable updates", residual replacement). Keeping p keeps the
+Krylov space that a restarted inner solve discards.
 """
 from __future__ import annotations
 
@@ -79,6 +86,51 @@ def defect_correction(disc: Discretization, b, outer_rtol=1e-10, inner_rtol=1e-5
         inner.append(k)
         x = x + d.astype(np.float64)
     return x, {"outer": len(inner), "inner_iters": inner, "rel_res": rel}
+
+
+def reliable_cg(disc: Discretization, b, rtol=1e-10, delta=1e-2, max_updates=100,
+                max_iters=100000):
+    """Returns (x, info) with info = dict(iters, updates, rel_res list)."""
+    dot = lambda a, c: float(np.dot(a.astype(np.float64), c.astype(np.float64)))
+    b = np.asarray(b, dtype=np.float64)
+    dinv32 = disc.jacobi_inverse(STIFF).astype(np.float32)
+    x = np.zeros_like(b)
+    bn = np.linalg.norm(b) or 1.0
+    r64 = b - disc.apply(STIFF, x)
+    rel = [float(np.linalg.norm(r64) / bn)]
+    r = r64.astype(np.float32)
+    x32 = np.zeros_like(r)
+    z = dinv32 * r
+    p = z.copy()
+    rz = dot(r, z)
+    ref = dot(r, r)
+    it = updates = 0
+    while rel[-1] > rtol and it < max_iters and updates < max_updates:
+        w = apply_stiff_f32(disc, p)
+        pw = dot(p, w)
+        alpha = rz / pw if pw != 0 else 0.0
+        x32 = x32 + np.float32(alpha) * p
+        r = r - np.float32(alpha) * w
+        z = dinv32 * r
+        rz_new = dot(r, z)
+        it += 1
+        if dot(r, r) <= delta * delta * ref or it == max_iters:
+            # reliable update: FP64 solution and true residual; p is kept
+            x = x + x32.astype(np.float64)
+            x32[:] = 0
+            r64 = b - disc.apply(STIFF, x)
+            rel.append(float(np.linalg.norm(r64) / bn))
+            updates += 1
+            r = r64.astype(np.float32)
+            z = dinv32 * r
+            rz_new = dot(r, z)
+            ref = dot(r, r)
+            if rel[-1] <= rtol:
+                break
+        beta = rz_new / rz if rz != 0 else 0.0
+        p = z + np.float32(beta) * p
+        rz = rz_new
+    return x, {"iters": it, "updates": updates, "rel_res": rel}
 
 
 def solve_fp64(disc: Discretization, b, rtol):

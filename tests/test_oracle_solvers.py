@@ -124,6 +124,24 @@ def test_defect_correction_reaches_fp64_tolerance():
     assert rel_err(x, x64) < 1e-7
 
 
+def test_reliable_update_cg_keeps_the_krylov_space():
+    # FP32 CG with FP64 residual replacement: reaches the FP64 tolerance in
+    # about the FP64 iteration count, where restarted defect correction
+    # needs its inner solves' sum of iterations (a variant that resets p at
+    # each substitution needs more than twice the FP64 count here)
+    disc, mesh = make_disc(5, 5, 4, 4, 4, seed=4)
+    b = manufactured_rhs(disc, mesh)
+    x, info = mixed.reliable_cg(disc, b, rtol=1e-10, delta=1e-2)
+    assert info["rel_res"][-1] <= 1e-10 and info["updates"] >= 2
+    r = b - assemble(disc, STIFF) @ x
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    x64, i64 = mixed.solve_fp64(disc, b, 1e-10)
+    assert rel_err(x, x64) < 1e-7
+    assert info["iters"] <= 1.25 * i64["iters"], (info["iters"], i64["iters"])
+    _, dc = mixed.defect_correction(disc, b, outer_rtol=1e-10, inner_rtol=1e-5)
+    assert sum(dc["inner_iters"]) > info["iters"]
+
+
 def _kappa(disc, mesh, seed=21):
     from oracle.geometry import quad_points
     return synth.kappa_log(quad_points(disc.rule, mesh.node_xyz), seed)
