@@ -194,11 +194,19 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol,
 
 /*
  * bp_pcg_solve_mixed -- FP64 defect correction around an FP32 Jacobi-PCG
- * (stiffness only; needs BP_SETUP_FP32). Outer step: r = b - A x in FP64,
- * stop when ||r||/||b|| <= outer_rtol; else solve A d = r in FP32 (vectors,
- * geometric factors and operator in FP32, dot products accumulated in FP64)
- * to inner_rtol or max_inner iterations, x += d in FP64.
- * b, x: device double; synchronises the stream before return.
+ * (stiffness only; needs BP_SETUP_FP32). Two modes (bp_set_option
+ * BP_OPT_MIXED_MODE):
+ *   BP_MIXED_RESTART (default): outer step r = b - A x in FP64, stop when
+ *     ||r||/||b|| <= outer_rtol; else solve A d = r in FP32 (vectors,
+ *     geometric factors and operator in FP32, dot products accumulated in
+ *     FP64) to inner_rtol or max_inner iterations, x += d in FP64.
+ *   BP_MIXED_RELIABLE: one FP32 Jacobi-PCG whose search direction is kept;
+ *     each time its recursive residual has dropped by the factor inner_rtol,
+ *     x += x32 in FP64 and the FP64 residual b - A x replaces the FP32 one
+ *     (at most max_outer replacements, max_inner FP32 iterations in all).
+ * Stats: iters = FP32 iterations, outer = outer steps or replacements.
+ * b, x: device double [ncomp][nglobal] (entries of b on Dirichlet nodes are
+ * read as 0); synchronises the stream before return.
  */
 int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
                        double inner_rtol, int max_outer, int max_inner,
@@ -223,6 +231,11 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
  * Unknown options return BP_ERR_ARG.
  */
 #define BP_OPT_TIME_APPLY 1
+/*   BP_OPT_MIXED_MODE: BP_MIXED_RESTART (0, default) or BP_MIXED_RELIABLE (1),
+ *   the algorithm of bp_pcg_solve_mixed. */
+#define BP_OPT_MIXED_MODE 2
+#define BP_MIXED_RESTART 0
+#define BP_MIXED_RELIABLE 1
 int bp_set_option(bp_op op, int option, int value);
 
 /* Free every buffer of the operator (synchronises the device first). */

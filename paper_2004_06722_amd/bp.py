@@ -174,9 +174,15 @@ class Operator:
 
     def pcg_solve_mixed(self, b: torch.Tensor, x: torch.Tensor | None = None,
                         outer_rtol: float = 1e-10, inner_rtol: float = 1e-5,
-                        max_outer: int = 50, max_inner: int = 2000):
+                        max_outer: int = 50, max_inner: int = 2000, reliable: bool = False):
+        """FP32-inner solve with FP64 corrections (bp_pcg_solve_mixed): restarted
+        defect correction, or with reliable=True one FP32 CG with FP64 residual
+        replacement whenever its residual has dropped by inner_rtol."""
         self._vec(b, name="b")
         x = torch.zeros_like(b) if x is None else self._vec(x, name="x")
+        check(self._lib.bp_set_option(self._h, _lib.BP_OPT_MIXED_MODE,
+                                      _lib.BP_MIXED_RELIABLE if reliable else
+                                      _lib.BP_MIXED_RESTART))
         st = PcgStats()
         check(self._lib.bp_pcg_solve_mixed(self._h, _ptr(b), _ptr(x), float(outer_rtol),
                                            float(inner_rtol), int(max_outer), int(max_inner),

@@ -50,6 +50,7 @@ constexpr int kMaxComp = 8;
 constexpr int kMaxTimedApplies = 4096;
 struct DevScalars {
   double rz[kMaxComp], pap[kMaxComp], rr[kMaxComp], bb[kMaxComp];
+  double rzp[kMaxComp];  // r.z before the last update (used after a residual replacement)
   double alpha[kMaxComp], beta[kMaxComp];
   double tol2;
   int done;       // set when every component meets the tolerance
@@ -91,5 +92,6 @@ struct bp_op_s {
   bp::DevScalars *sc_host = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool time_apply = false;
+  int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
   std::vector<hipEvent_t> apply_ev;  // pairs around operator launches
 };

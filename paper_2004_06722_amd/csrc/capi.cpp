@@ -154,26 +154,32 @@ int download_scalars(bp_op op, hipStream_t s) {
 }
 
 // Jacobi-PCG on precision T. x0_zero: x is zero on entry (skips A x0).
+// resume: continue from the device scalars and the r, p, w (w zero) that a
+// previous call or cg_restart left, without the set-up (b, rtol unused).
 template <typename T>
 int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r, T *p, T *w,
             double rtol, int maxit, bool fixed, bool x0_zero, hipStream_t s, int *iters_out,
-            float *ms_out, double *apply_ms_out = nullptr, int *apply_count_out = nullptr) {
+            float *ms_out, double *apply_ms_out = nullptr, int *apply_count_out = nullptr,
+            bool resume = false) {
   const int nc = op->ncomp;
   const int64_t n = op->nglobal, nv = n * nc;
   const bool masked = op->has_dirichlet;
   const int64_t nb_apply = apply_rows(op, which), nb_vec = vec_blocks(n);
-  int rc = upload_scalars(op, rtol, fixed, s);
-  if (rc) return rc;
-  if constexpr (sizeof(T) == 8)
-    fill_f64((double *)w, nv, 0.0, s);
-  else
-    fill_f32((float *)w, nv, 0.0f, s);
-  if (!x0_zero) {
-    rc = launch_apply(op, which, f32, x, w, masked, nullptr, nullptr, s);
+  int rc = BP_OK;
+  if (!resume) {
+    rc = upload_scalars(op, rtol, fixed, s);
     if (rc) return rc;
+    if constexpr (sizeof(T) == 8)
+      fill_f64((double *)w, nv, 0.0, s);
+    else
+      fill_f32((float *)w, nv, 0.0f, s);
+    if (!x0_zero) {
+      rc = launch_apply(op, which, f32, x, w, masked, nullptr, nullptr, s);
+      if (rc) return rc;
+    }
+    cg_init<T>(nc, n, b, r, w, p, dinv, op->part, op->sc, s);
+    BP_HIP(hipGetLastError());
   }
-  cg_init<T>(nc, n, b, r, w, p, dinv, op->part, op->sc, s);
-  BP_HIP(hipGetLastError());
   BP_HIP(hipEventRecord(op->ev0, s));
   const int poll = 8;
   int it = 0, timed = 0;
@@ -223,6 +229,68 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   if (op->sc_host->nonfinite) return set_error(BP_ERR_NONFINITE, "non-finite value in CG reductions");
   if (op->sc_host->breakdown) return set_error(BP_ERR_BREAKDOWN, "CG breakdown: p.Ap < 0");
   return BP_OK;
+}
+
+// FP64 residual r = b - A x into op->r and its norms into the device scalars
+// (rr, bb); returns max_c ||r_c|| / ||b_c|| through *worst.
+int true_residual(bp_op op, const double *b, const double *x, double *worst, hipStream_t s) {
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal;
+  fill_f64(op->w, n * nc, 0.0, s);
+  int rc = launch_apply(op, BP_STIFF, false, x, op->w, op->has_dirichlet, nullptr, nullptr, s);
+  if (rc) return rc;
+  dc_residual(nc, n, b, op->r, op->w, op->dinv[1], op->part, op->sc, s);
+  rc = download_scalars(op, s);
+  if (rc) return rc;
+  double m = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const double bb = op->sc_host->bb[c] > 0 ? op->sc_host->bb[c] : 1.0;
+    const double rel = std::sqrt(op->sc_host->rr[c] / bb);
+    if (!std::isfinite(rel)) return set_error(BP_ERR_NONFINITE, "mixed solve: non-finite residual");
+    m = std::max(m, rel);
+  }
+  *worst = m;
+  return BP_OK;
+}
+
+// FP32 Jacobi-PCG with reliable updates: one FP32 iteration whose search
+// direction is kept for the whole solve; whenever the recursive FP32
+// residual has dropped by `delta` since the last replacement, x += x32 in
+// FP64, the FP64 residual b - A x replaces the FP32 one, and the pending
+// direction update uses it. Stops at the FP64 tolerance, after max_updates
+// replacements, or after max_iters FP32 iterations.
+int mixed_reliable(bp_op op, const double *b, double *x, double rtol, double delta,
+                   int max_updates, int max_iters, int *iters_out, int *updates_out,
+                   hipStream_t s) {
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal, nv = n * nc;
+  int updates = 0, iters = 0;
+  double worst = 0.0;
+  int rc = true_residual(op, b, x, &worst, s);
+  if (rc == BP_OK && worst > rtol && max_updates > 0) {
+    to_f32(op->r, op->r32, nv, s);
+    fill_f32(op->x32, nv, 0.0f, s);
+    bool resume = false;
+    for (;;) {
+      rc = pcg_run<float>(op, BP_STIFF, true, op->r32, op->x32, op->dinv32, op->r32, op->p32,
+                          op->w32, delta, max_iters - iters, false, true, s, &iters, nullptr,
+                          nullptr, nullptr, resume);
+      if (rc) break;
+      const bool reached = op->sc_host->done != 0;
+      dc_accumulate(nv, x, op->x32, s);
+      fill_f32(op->x32, nv, 0.0f, s);
+      ++updates;
+      rc = true_residual(op, b, x, &worst, s);
+      if (rc || worst <= rtol || updates >= max_updates || iters >= max_iters || !reached) break;
+      to_f32(op->r, op->r32, nv, s);
+      cg_restart<float>(nc, n, op->r32, op->p32, op->dinv32, op->part, op->sc, s);
+      BP_HIP(hipGetLastError());
+      resume = true;
+    }
+  }
+  *iters_out = iters;
+  *updates_out = updates;
+  return rc;
 }
 
 void fill_stats(bp_op op, double rtol, bp_pcg_stats *st) {
@@ -543,11 +611,14 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
   BP_HIP(hipEventCreate(&t1));
   BP_HIP(hipEventRecord(t0, s));
   int outer = 0, inner_total = 0;
-  for (;;) {
+  if (op->mixed_mode == BP_MIXED_RELIABLE) {
+    rc = mixed_reliable(op, b, x, outer_rtol, inner_rtol, max_outer, max_inner, &inner_total,
+                        &outer, s);
+  } else for (;;) {
     fill_f64(op->w, nv, 0.0, s);
     rc = launch_apply(op, BP_STIFF, false, x, op->w, masked, nullptr, nullptr, s);
     if (rc) break;
-    dc_residual(nc, n, b, op->r, op->w, op->part, op->sc, s);
+    dc_residual(nc, n, b, op->r, op->w, op->dinv[1], op->part, op->sc, s);
     rc = download_scalars(op, s);
     if (rc) break;
     double worst = 0.0;
@@ -600,6 +671,12 @@ int bp_set_option(bp_op op, int option, int value) {
   if (!op) return set_error(BP_ERR_ARG, "null operator");
   if (option == BP_OPT_TIME_APPLY) {
     op->time_apply = value != 0;
+    return BP_OK;
+  }
+  if (option == BP_OPT_MIXED_MODE) {
+    if (value != BP_MIXED_RESTART && value != BP_MIXED_RELIABLE)
+      return set_error(BP_ERR_ARG, "bp_set_option: unknown mixed-precision mode");
+    op->mixed_mode = value;
     return BP_OK;
   }
   return set_error(BP_ERR_ARG, "bp_set_option: unknown option " + std::to_string(option));

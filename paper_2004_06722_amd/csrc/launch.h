@@ -60,9 +60,17 @@ template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
                   hipStream_t s);
 
+// residual replacement after an iteration that stopped before its direction
+// update: r.z and r.r of the new residual r, then the pending p = z + beta p
+// with beta = (r.z)_new / (r.z)_old (the search direction is kept); r.r
+// becomes the reference norm; clears done/halted
+template <typename T>
+void cg_restart(int nc, int64_t n, const T *r, T *p, const T *dinv, double *part,
+                DevScalars *sc, hipStream_t s);
+
 // defect correction helpers (FP64 outer loop)
-void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,
-                 DevScalars *sc, hipStream_t s);
+void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
+                 double *part, DevScalars *sc, hipStream_t s);
 void dc_accumulate(int64_t n, double *x, const float *d, hipStream_t s);
 
 }  // namespace bp

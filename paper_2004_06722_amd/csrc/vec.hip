@@ -237,6 +237,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restri
     for (int c = 0; c < nc; ++c) {
       const double rz = res[c];
       sc->beta[c] = sc->rz[c] != 0.0 ? rz / sc->rz[c] : 0.0;
+      sc->rzp[c] = sc->rz[c];
       sc->rz[c] = rz;
       sc->rr[c] = res[nc + c];
       if (!isfinite(rz) || !isfinite(res[nc + c])) sc->nonfinite = 1;
@@ -267,21 +268,24 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xp(int64_t n, T *__re
   }
 }
 
-// r = b - w, w = 0; partials r.r and b.b
+// r = b - w, w = 0; partials r.r and b.b. As in k_cg_init, entries of b on
+// Dirichlet nodes (dinv = 0 there) are read as 0.
 __global__ __launch_bounds__(kVecThreads) void k_dc_residual(int64_t n, const double *__restrict__ b,
                                                              double *__restrict__ r,
                                                              double *__restrict__ w,
+                                                             const double *__restrict__ dinv,
                                                              double *__restrict__ part) {
   const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   double rr = 0.0, bb = 0.0;
   if (v < n) {
     const int64_t f = comp * n + v;
-    const double rv = b[f] - w[f];
+    const double bv = dinv[v] != 0.0 ? b[f] : 0.0;
+    const double rv = dinv[v] != 0.0 ? bv - w[f] : 0.0;
     r[f] = rv;
     w[f] = 0.0;
     rr = rv * rv;
-    bb = b[f] * b[f];
+    bb = bv * bv;
   }
   block_partial1(rr, part, 2 * nc, comp);
   block_partial1(bb, part, 2 * nc, nc + comp);
@@ -341,6 +345,38 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_geometry(const double *__
     Gk[i] = v;
     if (Gk32) Gk32[i] = (float)v;
   }
+}
+
+// p = dinv r + beta p: the direction update left pending by a residual
+// replacement (k_cg_update_xp skips it in the iteration that converged)
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_direction(int64_t n, T *__restrict__ p,
+                                                              const T *__restrict__ r,
+                                                              const T *__restrict__ dinv,
+                                                              const DevScalars *__restrict__ sc) {
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v < n) {
+    const int64_t f = blockIdx.y * n + v;
+    p[f] = dinv[v] * r[f] + (T)sc->beta[blockIdx.y] * p[f];
+  }
+}
+
+// Partials of r.z (z = dinv r) and r.r for a replaced residual (the search
+// direction is kept; see cg_restart).
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_dots(int64_t n, const T *__restrict__ r,
+                                                         const T *__restrict__ dinv,
+                                                         double *__restrict__ part) {
+  const int comp = blockIdx.y, nc = gridDim.y;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if (v < n) {
+    const T rv = r[comp * n + v];
+    rz = (double)rv * (double)(dinv[v] * rv);
+    rr = (double)rv * (double)rv;
+  }
+  block_partial1(rz, part, 2 * nc, comp);
+  block_partial1(rr, part, 2 * nc, nc + comp);
 }
 
 // Bb[i] = beta_i * Bt[i] with beta_i = beta_q[i], or beta if beta_q is NULL
@@ -405,7 +441,30 @@ void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk3
                      G, kappa, Gk, Gk32, nelem, nq);
 }
 
-enum class FinKind { Init, Alpha, Beta, Norms };
+// after a residual replacement that ended an iteration before its direction
+// update: r.z and r.r of the new residual, beta = (r.z)_new / (r.z) of the
+// iteration (for the pending p = z + beta p); r.r also becomes the reference
+// for the next relative reduction; the loop flags are cleared
+template <int NC>
+__global__ __launch_bounds__(kFinThreads) void k_fin_restart(const double *__restrict__ part,
+                                                             int64_t nb, DevScalars *sc) {
+  __shared__ double res[2 * NC];
+  reduce_columns<2 * NC>(part, nb, res);
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int c = 0; c < NC; ++c) {
+      sc->beta[c] = sc->rzp[c] != 0.0 ? res[c] / sc->rzp[c] : 0.0;
+      sc->rz[c] = res[c];
+      sc->rr[c] = sc->bb[c] = res[NC + c];
+      bad |= !isfinite(res[c]) || !isfinite(res[NC + c]);
+    }
+    sc->nonfinite = bad;
+    sc->done = bad;
+    sc->halted = bad;
+  }
+}
+
+enum class FinKind { Init, Alpha, Beta, Norms, Restart };
 
 // the single-work-group finisher for nc components (compile-time widths)
 template <int NC>
@@ -423,6 +482,9 @@ static void launch_fin_nc(FinKind k, const double *src, int64_t rows, DevScalars
       break;
     case FinKind::Norms:
       hipLaunchKernelGGL(k_fin_norms<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      break;
+    case FinKind::Restart:
+      hipLaunchKernelGGL(k_fin_restart<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
       break;
   }
 }
@@ -485,14 +547,32 @@ void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevS
                      p, r, dinv, sc);
 }
 
-void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, double *part,
-                 DevScalars *sc, hipStream_t s) {
+void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
+                 double *part, DevScalars *sc, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_dc_residual, dim3(nb, nc), dim3(kVecThreads), 0, s, n, b, r, w, part);
+  hipLaunchKernelGGL(k_dc_residual, dim3(nb, nc), dim3(kVecThreads), 0, s, n, b, r, w, dinv,
+                     part);
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, 2 * nc, part + nb * 2 * nc, &rows, s);
   launch_fin(FinKind::Norms, nc, src, rows, sc, s);
 }
+
+template <typename T>
+void cg_restart(int nc, int64_t n, const T *r, T *p, const T *dinv, double *part,
+                DevScalars *sc, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_cg_dots<T>), dim3(nb, nc), dim3(kVecThreads), 0, s, n, r, dinv, part);
+  int64_t rows = 0;
+  const double *src = reduce_stage1(part, nb, 2 * nc, part + nb * 2 * nc, &rows, s);
+  launch_fin(FinKind::Restart, nc, src, rows, sc, s);
+  hipLaunchKernelGGL((k_cg_direction<T>), dim3(nb, nc), dim3(kVecThreads), 0, s, n, p, r, dinv,
+                     sc);
+}
+
+template void cg_restart<float>(int, int64_t, const float *, float *, const float *, double *,
+                                DevScalars *, hipStream_t);
+template void cg_restart<double>(int, int64_t, const double *, double *, const double *,
+                                 double *, DevScalars *, hipStream_t);
 
 void dc_accumulate(int64_t n, double *x, const float *d, hipStream_t s) {
   hipLaunchKernelGGL(k_accumulate, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, x, d, n);

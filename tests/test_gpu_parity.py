@@ -213,6 +213,32 @@ def test_mixed_precision_defect_correction():
         c.close()
 
 
+@pytest.mark.parametrize("ncomp", [1, 3])
+def test_mixed_precision_reliable_updates(ncomp):
+    # FP32 CG with FP64 residual replacement: FP64 accuracy in about the FP64
+    # iteration count (the oracle's same algorithm and the FP64 solve decide)
+    c = Case(5, 5, 4, 4, 4, seed=4, fp32=True, ncomp=ncomp)
+    try:
+        b1 = manufactured_rhs(c)
+        b = np.stack([b1 * (1 + 0.5 * k) for k in range(ncomp)], axis=1) if ncomp > 1 else b1
+        x, st = c.op.pcg_solve_mixed(dev(b), outer_rtol=1e-10, inner_rtol=1e-2,
+                                     max_outer=100, max_inner=5000, reliable=True)
+        xg = host(x)
+        assert st["converged"] and st["outer"] >= 2
+        x64, i64 = mixed.solve_fp64(c.disc, b1, 1e-10)
+        xo, io = mixed.reliable_cg(c.disc, b1, rtol=1e-10, delta=1e-2)
+        for k in range(ncomp):
+            xk = xg[:, k] / (1 + 0.5 * k) if ncomp > 1 else xg
+            r = b1 - c.disc.apply(STIFF, xk)
+            assert np.linalg.norm(r) / np.linalg.norm(b1) <= 1.2e-10
+            assert rel(xk, x64) < 1e-8
+        # same algorithm as the oracle: FP32 rounding moves the count a little
+        assert abs(st["iters"] - io["iters"]) <= 0.1 * io["iters"] + 3, (st["iters"], io["iters"])
+        assert st["iters"] <= 1.25 * i64["iters"]
+    finally:
+        c.close()
+
+
 def test_grad_kappa_matches_oracle():
     from oracle.geometry import quad_points
     c = Case(5, 5, 3, 2, 2, seed=11, ncomp=2)
