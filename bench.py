@@ -250,13 +250,18 @@ def workload_mixed(args):
     t64 = time.perf_counter() - t0
     log(f"FP64 PCG: {st64['iters']} iterations, {t64:.2f} s")
     runs = []
+    # reliable updates need the FP32 recursion to stay close to the true
+    # residual between replacements: at this conditioning a reduction of 1e-2
+    # or more between replacements lets it drift (13k iterations at 1e-2), so
+    # the sweep stays at 0.1-0.3 and the FP32 iteration budget at 3x FP64
     cases = [("restart", t) for t in (1e-5, 1e-4, 1e-3, 1e-2, 1e-1)] + \
-            [("reliable", t) for t in (1e-1, 1e-2, 1e-3)]
+            [("reliable", t) for t in (3e-1, 2e-1, 1e-1, 5e-2)]
     for mode, inner in cases:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         xm, stm = op.pcg_solve_mixed(b, outer_rtol=1e-10, inner_rtol=inner, max_outer=1000,
-                                     max_inner=100000, reliable=mode == "reliable")
+                                     max_inner=100000 if mode == "restart" else 3 * st64["iters"],
+                                     reliable=mode == "reliable")
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0
         runs.append({"mode": mode, "inner_rtol": inner, "seconds": tm, "outer": stm["outer"],
