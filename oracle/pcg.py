@@ -64,3 +64,50 @@ def pcg(apply_A, b, dinv, x0=None, rtol=0.0, maxit=100, fixed_iters=False,
         if record is not None:
             record.append(x.copy())
     return x, {"iters": it, "rel_res": rel}
+
+
+def pcg_single_reduction(apply_A, b, dinv, x0=None, rtol=0.0, maxit=100, fixed_iters=False,
+                         record=None):
+    """Jacobi-PCG with one reduction phase per iteration (Chronopoulos-Gear
+    recurrences): the same iterates as pcg in exact arithmetic. With u = D^-1 r
+    and w = A u it carries s = A p by recurrence, so that gamma = (r, u) and
+    delta = (u, w) come from the same pass:
+        p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s, u = D^-1 r,
+        w = A u, gamma' = (r, u), delta = (u, w), beta = gamma'/gamma,
+        alpha = gamma' / (delta - beta gamma' / alpha).
+    Arguments and return value as pcg."""
+    b = np.asarray(b, dtype=np.float64)
+    d = dinv.reshape((-1,) + (1,) * (b.ndim - 1))
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    u = d * r
+    w = apply_A(u)
+    gamma = _dot(r, u)
+    delta = _dot(u, w)
+    alpha = _safe_div(gamma, delta)
+    beta = np.zeros_like(gamma)
+    p = np.zeros_like(b)
+    s = np.zeros_like(b)
+    bnorm = np.sqrt(_dot(b, b))
+    bnorm = np.where(bnorm == 0, 1.0, bnorm)
+    rel = [float(np.max(np.sqrt(_dot(r, r)) / bnorm))]
+    it = 0
+    while it < maxit:
+        if not fixed_iters and rel[-1] <= rtol:
+            break
+        p = u + beta * p
+        s = w + beta * s
+        x = x + alpha * p
+        r = r - alpha * s
+        u = d * r
+        w = apply_A(u)
+        gamma_new = _dot(r, u)
+        delta = _dot(u, w)
+        beta = _safe_div(gamma_new, gamma)
+        alpha = _safe_div(gamma_new, delta - beta * _safe_div(gamma_new, alpha))
+        gamma = gamma_new
+        it += 1
+        rel.append(float(np.max(np.sqrt(_dot(r, r)) / bnorm)))
+        if record is not None:
+            record.append(x.copy())
+    return x, {"iters": it, "rel_res": rel}

@@ -7,7 +7,7 @@ import synth
 from oracle import adjoint, mixed
 from oracle.assembled import assemble, d_stiffness_d_kappa
 from oracle.operators import MASS, STIFF
-from oracle.pcg import pcg
+from oracle.pcg import pcg, pcg_single_reduction
 from tests.oracle_cases import make_disc, rel_err
 
 
@@ -199,3 +199,30 @@ def test_adjoint_gradient_finite_differences():
         fd = (Ls[0] - Ls[1]) / (2 * eps)
         an = float(np.sum(g * dlt))
         assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_single_reduction_pcg_has_the_same_iterates():
+    # the Chronopoulos-Gear recurrences reproduce standard PCG's iterates (to
+    # rounding), reach the direct solution, and handle several components
+    disc, mesh = config1()
+    b = manufactured_rhs(disc, mesh)
+    dinv = disc.jacobi_inverse(STIFF)
+    A = lambda v: disc.apply(STIFF, v)
+    ref, sr = [], []
+    pcg(A, b, dinv, maxit=12, fixed_iters=True, record=ref)
+    pcg_single_reduction(A, b, dinv, maxit=12, fixed_iters=True, record=sr)
+    for k in range(12):
+        assert rel_err(sr[k], ref[k]) < 1e-12, k
+    x, info = pcg_single_reduction(A, b, dinv, rtol=1e-13, maxit=2000)
+    inner = mesh.boundary == 0
+    Ad = assemble(disc, STIFF).tocsr()[inner][:, inner]
+    xd = np.zeros_like(b)
+    xd[inner] = spla.spsolve(Ad.tocsc(), b[inner])
+    assert rel_err(x, xd) < 1e-11
+    _, info_std = pcg(A, b, dinv, rtol=1e-13, maxit=2000)
+    assert abs(info["iters"] - info_std["iters"]) <= 1
+    B = np.stack([b, 2 * b + 0.1 * disc.mask], axis=1)
+    r2, s2 = [], []
+    pcg(A, B, dinv, maxit=6, fixed_iters=True, record=r2)
+    pcg_single_reduction(A, B, dinv, maxit=6, fixed_iters=True, record=s2)
+    assert rel_err(s2[-1], r2[-1]) < 1e-12
