@@ -236,6 +236,18 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
 #define BP_OPT_MIXED_MODE 2
 #define BP_MIXED_RESTART 0
 #define BP_MIXED_RELIABLE 1
+/*   BP_OPT_CG_VARIANT: the PCG recurrences of bp_pcg_solve.
+ *     BP_CG_STANDARD (0, default): two reduction phases per iteration (alpha
+ *       from p.Ap after the operator, beta from r.z after the residual update).
+ *     BP_CG_SINGLE_REDUCTION (1): Chronopoulos-Gear recurrences -- s = A p
+ *       by recurrence, one fused vector pass and one reduction phase per
+ *       iteration (three launches instead of five for small meshes; the
+ *       iterates are those of the standard form up to rounding, section 3's
+ *       Jacobi-PCG in exact arithmetic). Allocates one more vector on first
+ *       use. */
+#define BP_OPT_CG_VARIANT 3
+#define BP_CG_STANDARD 0
+#define BP_CG_SINGLE_REDUCTION 1
 int bp_set_option(bp_op op, int option, int value);
 
 /* Free every buffer of the operator (synchronises the device first). */

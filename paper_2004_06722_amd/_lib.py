@@ -17,6 +17,8 @@ BP_SETUP_FP32 = 1
 BP_OPT_TIME_APPLY = 1
 BP_OPT_MIXED_MODE = 2
 BP_MIXED_RESTART, BP_MIXED_RELIABLE = 0, 1
+BP_OPT_CG_VARIANT = 3
+BP_CG_STANDARD, BP_CG_SINGLE_REDUCTION = 0, 1
 
 ERROR_NAMES = {BP_ERR_ARG: "BP_ERR_ARG", BP_ERR_MESH: "BP_ERR_MESH", BP_ERR_HIP: "BP_ERR_HIP",
                BP_ERR_NONFINITE: "BP_ERR_NONFINITE", BP_ERR_BREAKDOWN: "BP_ERR_BREAKDOWN",

@@ -146,6 +146,12 @@ class Operator:
     def set_option(self, option: int, value: int):
         check(self._lib.bp_set_option(self._h, option, value))
 
+    def set_cg_variant(self, single_reduction: bool):
+        """PCG recurrences of pcg_solve: standard (two reduction phases per
+        iteration) or single-reduction (Chronopoulos-Gear)."""
+        self.set_option(_lib.BP_OPT_CG_VARIANT, _lib.BP_CG_SINGLE_REDUCTION if single_reduction
+                        else _lib.BP_CG_STANDARD)
+
     def set_coeff(self, kappa: torch.Tensor | None):
         if kappa is not None:
             if kappa.dtype != torch.float64 or kappa.device.type != "cuda" or \

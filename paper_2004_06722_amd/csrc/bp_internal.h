@@ -93,5 +93,7 @@ struct bp_op_s {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool time_apply = false;
   int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
+  int cg_variant = 0;  // BP_CG_STANDARD or BP_CG_SINGLE_REDUCTION (bp_pcg_solve)
+  double *sv = nullptr;  // s = A p of the single-reduction PCG (allocated on first use)
   std::vector<hipEvent_t> apply_ev;  // pairs around operator launches
 };

@@ -64,6 +64,7 @@ void release(bp_op op) {
   dfree(op->w);
   dfree(op->part);
   dfree(op->tmp);
+  dfree(op->sv);
   dfree(op->r32);
   dfree(op->p32);
   dfree(op->w32);
@@ -228,6 +229,85 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   }
   if (op->sc_host->nonfinite) return set_error(BP_ERR_NONFINITE, "non-finite value in CG reductions");
   if (op->sc_host->breakdown) return set_error(BP_ERR_BREAKDOWN, "CG breakdown: p.Ap < 0");
+  return BP_OK;
+}
+
+// Single-reduction Jacobi-PCG (FP64): per iteration the fused vector update,
+// the operator on u = dinv r (its energy partials give (u, A u)) and one
+// finisher. u lives in op->tmp, s = A p in op->sv. Same timing and stopping
+// conventions as pcg_run; x0_zero skips the operator on x0.
+int pcg_run_sr(bp_op op, int which, const double *b, double *x, const double *dinv,
+               double rtol, int maxit, bool fixed, bool x0_zero, hipStream_t s,
+               int *iters_out, float *ms_out, double *apply_ms_out, int *apply_count_out) {
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal, nv = n * nc;
+  const bool masked = op->has_dirichlet;
+  const int64_t nba = apply_rows(op, which), nbv = vec_blocks(n);
+  double *pv = op->part;                                     // vector partials + stage 1
+  double *pa = op->part + (nbv + kStage2Rows) * 3 * nc;      // operator partials + stage 1
+  double *r = op->r, *u = op->tmp, *w = op->w, *p = op->pv, *sv = op->sv;
+  int rc = upload_scalars(op, rtol, fixed, s);
+  if (rc) return rc;
+  fill_f64(w, nv, 0.0, s);
+  if (!x0_zero) {
+    rc = launch_apply(op, which, false, x, w, masked, nullptr, nullptr, s);
+    if (rc) return rc;
+  }
+  sr_init<double>(nc, n, b, r, w, u, p, sv, dinv, pv, s);
+  rc = launch_apply(op, which, false, u, w, masked, pa, nullptr, s);
+  if (rc) return rc;
+  sr_fin(true, nc, pv, nbv, pa, nba, op->sc, s);
+  BP_HIP(hipGetLastError());
+  BP_HIP(hipEventRecord(op->ev0, s));
+  const int poll = 8;
+  int it = 0, timed = 0;
+  const int *done = &op->sc->done;
+  if (op->time_apply && op->apply_ev.empty()) {
+    op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
+    for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
+  }
+  while (it < maxit) {
+    const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
+    for (int c = 0; c < chunk; ++c) {
+      sr_update<double>(nc, n, x, r, u, w, p, sv, dinv, pv, op->sc, s);
+      // the operator and finisher of the last fixed iteration would only
+      // prepare a step that is not taken
+      if (fixed && it + c == maxit - 1) break;
+      const bool tm = op->time_apply && timed < kMaxTimedApplies;
+      if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
+      rc = launch_apply(op, which, false, u, w, masked, pa, done, s);
+      if (rc) return rc;
+      if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
+      sr_fin(false, nc, pv, nbv, pa, nba, op->sc, s);
+    }
+    BP_HIP(hipGetLastError());
+    it += chunk;
+    if (!fixed) {
+      rc = download_scalars(op, s);
+      if (rc) return rc;
+      if (op->sc_host->done) break;
+    }
+  }
+  BP_HIP(hipEventRecord(op->ev1, s));
+  rc = download_scalars(op, s);
+  if (rc) return rc;
+  float ms = 0.0f;
+  BP_HIP(hipEventElapsedTime(&ms, op->ev0, op->ev1));
+  if (ms_out) *ms_out = ms;
+  // fixed mode skips the last finisher, which would have counted the last step
+  if (iters_out) *iters_out = fixed ? maxit : op->sc_host->iters;
+  if (apply_ms_out) {
+    double sum = 0.0;
+    for (int k = 0; k < timed; ++k) {
+      float t = 0.0f;
+      BP_HIP(hipEventElapsedTime(&t, op->apply_ev[2 * k], op->apply_ev[2 * k + 1]));
+      sum += t;
+    }
+    *apply_ms_out = sum;
+    if (apply_count_out) *apply_count_out = timed;
+  }
+  if (op->sc_host->nonfinite) return set_error(BP_ERR_NONFINITE, "non-finite value in CG reductions");
+  if (op->sc_host->breakdown) return set_error(BP_ERR_BREAKDOWN, "CG breakdown: non-positive curvature");
   return BP_OK;
 }
 
@@ -428,8 +508,7 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRY(dmalloc(&op->tmp, std::max<int64_t>(nv, nglobal)));
   // partial sums of the largest grid, followed by the stage-1 rows
   op->part_len =
-      std::max<int64_t>(max_partial_rows(op) * ncomp, vec_blocks(nglobal) * 3 * ncomp) +
-      kStage2Rows * 3 * ncomp;
+      (vec_blocks(nglobal) + kStage2Rows) * 3 * ncomp + (max_partial_rows(op) + kStage2Rows) * ncomp;
   TRY(dmalloc(&op->part, op->part_len));
   TRY(dmalloc(&op->sc, 1));
   TRYHIP(hipHostMalloc((void **)&op->sc_host, sizeof(DevScalars), hipHostMallocDefault));
@@ -577,9 +656,18 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
   float ms = 0.0f;
   double apply_ms = 0.0;
   int apply_count = 0;
-  rc = pcg_run<double>(op, which, false, b, x, op->dinv[dinv_slot(which)], op->r, op->pv,
-                       op->w, rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
-                       &apply_count);
+  if (op->cg_variant == BP_CG_SINGLE_REDUCTION) {
+    if (!op->sv) {
+      rc = dmalloc(&op->sv, op->nglobal * op->ncomp);
+      if (rc) return rc;
+    }
+    rc = pcg_run_sr(op, which, b, x, op->dinv[dinv_slot(which)], rtol, maxit, fixed_iters != 0,
+                    false, s, &iters, &ms, &apply_ms, &apply_count);
+  } else {
+    rc = pcg_run<double>(op, which, false, b, x, op->dinv[dinv_slot(which)], op->r, op->pv,
+                         op->w, rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
+                         &apply_count);
+  }
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->iters = iters;
@@ -671,6 +759,12 @@ int bp_set_option(bp_op op, int option, int value) {
   if (!op) return set_error(BP_ERR_ARG, "null operator");
   if (option == BP_OPT_TIME_APPLY) {
     op->time_apply = value != 0;
+    return BP_OK;
+  }
+  if (option == BP_OPT_CG_VARIANT) {
+    if (value != BP_CG_STANDARD && value != BP_CG_SINGLE_REDUCTION)
+      return set_error(BP_ERR_ARG, "bp_set_option: unknown CG variant");
+    op->cg_variant = value;
     return BP_OK;
   }
   if (option == BP_OPT_MIXED_MODE) {

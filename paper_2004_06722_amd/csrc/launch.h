@@ -60,6 +60,18 @@ template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
                   hipStream_t s);
 
+// single-reduction PCG: init (r, u = dinv r, p = s = w = 0; partials r.u, r.r,
+// b.b), the fused vector update (partials r.u, r.r), and the finisher that
+// combines them with the operator's (u, A u) partials (alpha, beta, flags)
+template <typename T>
+void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const T *dinv,
+             double *part, hipStream_t s);
+template <typename T>
+void sr_update(int nc, int64_t n, T *x, T *r, T *u, T *w, T *p, T *sv, const T *dinv,
+               double *part, DevScalars *sc, hipStream_t s);
+void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba,
+            DevScalars *sc, hipStream_t s);
+
 // residual replacement after an iteration that stopped before its direction
 // update: r.z and r.r of the new residual r, then the pending p = z + beta p
 // with beta = (r.z)_new / (r.z)_old (the search direction is kept); r.r

@@ -347,6 +347,123 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_geometry(const double *__
   }
 }
 
+// ---- single-reduction PCG (Chronopoulos-Gear recurrences) -----------------
+// With u = dinv r, w = A u and s = A p carried by recurrence, (r, u) comes
+// from the vector pass and (u, w) from the operator's fused energy, so one
+// finisher per iteration computes alpha and beta.
+
+// r = b - w (w = A x0), u = dinv r, p = s = 0, w = 0; partials r.u, r.r, b.b
+// (entries of b on Dirichlet nodes read as 0)
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_sr_init(int64_t n, const T *__restrict__ b,
+                                                         T *__restrict__ r, T *__restrict__ w,
+                                                         T *__restrict__ u, T *__restrict__ p,
+                                                         T *__restrict__ sv,
+                                                         const T *__restrict__ dinv,
+                                                         double *__restrict__ part) {
+  const int comp = blockIdx.y, nc = gridDim.y;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double ru = 0.0, rr = 0.0, bb = 0.0;
+  if (v < n) {
+    const int64_t f = comp * n + v;
+    const T di = dinv[v];
+    const bool free = di != T(0);
+    const T bv = free ? b[f] : T(0);
+    const T rv = free ? bv - w[f] : T(0);
+    const T uv = di * rv;
+    r[f] = rv;
+    u[f] = uv;
+    p[f] = T(0);
+    sv[f] = T(0);
+    w[f] = T(0);
+    ru = (double)rv * (double)uv;
+    rr = (double)rv * (double)rv;
+    bb = (double)bv * (double)bv;
+  }
+  block_partial1(ru, part, 3 * nc, comp);
+  block_partial1(rr, part, 3 * nc, nc + comp);
+  block_partial1(bb, part, 3 * nc, 2 * nc + comp);
+}
+
+// p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s; u = dinv r;
+// w = 0; partials r.u and r.r
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_sr_update(
+    int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ u, T *__restrict__ w,
+    T *__restrict__ p, T *__restrict__ sv, const T *__restrict__ dinv, double *__restrict__ part,
+    const DevScalars *__restrict__ sc) {
+  if (sc->done) return;
+  const int comp = blockIdx.y, nc = gridDim.y;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double ru = 0.0, rr = 0.0;
+  if (v < n) {
+    const int64_t f = comp * n + v;
+    const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
+    const T pv = u[f] + be * p[f];
+    const T s = w[f] + be * sv[f];
+    p[f] = pv;
+    sv[f] = s;
+    x[f] += al * pv;
+    const T rv = r[f] - al * s;
+    const T uv = dinv[v] * rv;
+    r[f] = rv;
+    u[f] = uv;
+    w[f] = T(0);
+    ru = (double)rv * (double)uv;
+    rr = (double)rv * (double)rv;
+  }
+  block_partial1(ru, part, 2 * nc, comp);
+  block_partial1(rr, part, 2 * nc, nc + comp);
+}
+
+// first: gamma, r.r, b.b from the vector pass, delta = (u, A u) from the
+// operator; alpha = gamma / delta, beta = 0. Later: beta = gamma' / gamma,
+// alpha = gamma' / (delta - beta gamma' / alpha); convergence on r.r.
+template <int NC, bool FIRST>
+__global__ __launch_bounds__(kFinThreads) void k_fin_sr(const double *__restrict__ pv,
+                                                        int64_t nbv,
+                                                        const double *__restrict__ pa,
+                                                        int64_t nba, DevScalars *sc) {
+  if (!FIRST && sc->done) return;
+  constexpr int WV = FIRST ? 3 * NC : 2 * NC;
+  __shared__ double rv[WV];
+  __shared__ double ra[NC];
+  reduce_columns<WV>(pv, nbv, rv);
+  reduce_columns<NC>(pa, nba, ra);
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int c = 0; c < NC; ++c) {
+      const double g = rv[c], delta = ra[c];
+      double alpha, beta = 0.0;
+      if (FIRST) {
+        alpha = delta != 0.0 ? g / delta : 0.0;
+        sc->bb[c] = rv[2 * NC + c];
+        if (delta < 0.0) sc->breakdown = 1;
+      } else {
+        beta = sc->rz[c] != 0.0 ? g / sc->rz[c] : 0.0;
+        const double den = delta - (sc->alpha[c] != 0.0 ? beta * g / sc->alpha[c] : 0.0);
+        alpha = den != 0.0 ? g / den : 0.0;
+        if (den < 0.0) sc->breakdown = 1;
+      }
+      sc->rz[c] = g;
+      sc->pap[c] = delta;
+      sc->rr[c] = rv[NC + c];
+      sc->alpha[c] = alpha;
+      sc->beta[c] = beta;
+      bad |= !isfinite(g) || !isfinite(delta) || !isfinite(rv[NC + c]);
+    }
+    if (FIRST) {
+      sc->iters = 0;
+      sc->breakdown = sc->breakdown && !bad;
+      sc->halted = 0;
+    } else {
+      sc->iters += 1;
+    }
+    sc->nonfinite = bad;
+    sc->done = bad || (!sc->fixed && converged(sc, NC));
+  }
+}
+
 // p = dinv r + beta p: the direction update left pending by a residual
 // replacement (k_cg_update_xp skips it in the iteration that converged)
 template <typename T>
@@ -556,6 +673,54 @@ void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const
   const double *src = reduce_stage1(part, nb, 2 * nc, part + nb * 2 * nc, &rows, s);
   launch_fin(FinKind::Norms, nc, src, rows, sc, s);
 }
+
+template <typename T>
+void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const T *dinv,
+             double *part, hipStream_t s) {
+  hipLaunchKernelGGL((k_sr_init<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, b, r,
+                     w, u, p, sv, dinv, part);
+}
+
+template <typename T>
+void sr_update(int nc, int64_t n, T *x, T *r, T *u, T *w, T *p, T *sv, const T *dinv,
+               double *part, DevScalars *sc, hipStream_t s) {
+  hipLaunchKernelGGL((k_sr_update<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x, r,
+                     u, w, p, sv, dinv, part, sc);
+}
+
+template <int NC>
+static void launch_fin_sr_nc(bool first, const double *pv, int64_t nbv, const double *pa,
+                             int64_t nba, DevScalars *sc, hipStream_t s) {
+  if (first)
+    hipLaunchKernelGGL((k_fin_sr<NC, true>), dim3(1), dim3(kFinThreads), 0, s, pv, nbv, pa, nba,
+                       sc);
+  else
+    hipLaunchKernelGGL((k_fin_sr<NC, false>), dim3(1), dim3(kFinThreads), 0, s, pv, nbv, pa, nba,
+                       sc);
+}
+
+void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba,
+            DevScalars *sc, hipStream_t s) {
+  const int wv = (first ? 3 : 2) * nc;
+  int64_t rv = 0, ra = 0;
+  const double *sv = reduce_stage1(pv, nbv, wv, pv + nbv * wv, &rv, s);
+  const double *sa = reduce_stage1(pa, nba, nc, pa + nba * nc, &ra, s);
+  switch (nc) {
+    case 1: launch_fin_sr_nc<1>(first, sv, rv, sa, ra, sc, s); break;
+    case 2: launch_fin_sr_nc<2>(first, sv, rv, sa, ra, sc, s); break;
+    case 3: launch_fin_sr_nc<3>(first, sv, rv, sa, ra, sc, s); break;
+    case 4: launch_fin_sr_nc<4>(first, sv, rv, sa, ra, sc, s); break;
+    case 5: launch_fin_sr_nc<5>(first, sv, rv, sa, ra, sc, s); break;
+    case 6: launch_fin_sr_nc<6>(first, sv, rv, sa, ra, sc, s); break;
+    case 7: launch_fin_sr_nc<7>(first, sv, rv, sa, ra, sc, s); break;
+    default: launch_fin_sr_nc<kMaxComp>(first, sv, rv, sa, ra, sc, s); break;
+  }
+}
+
+template void sr_init<double>(int, int64_t, const double *, double *, double *, double *,
+                              double *, double *, const double *, double *, hipStream_t);
+template void sr_update<double>(int, int64_t, double *, double *, double *, double *, double *,
+                                double *, const double *, double *, DevScalars *, hipStream_t);
 
 template <typename T>
 void cg_restart(int nc, int64_t n, const T *r, T *p, const T *dinv, double *part,

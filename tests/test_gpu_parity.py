@@ -132,6 +132,35 @@ def test_pcg_iterates_match_oracle_orders(bp, p, ncomp):
         c.close()
 
 
+@pytest.mark.parametrize("bp,p,ncomp", [(5, 3, 1), (5, 7, 1), (5, 4, 3), (3, 5, 1), (1, 4, 1),
+                                         (5, 1, 2)])
+def test_single_reduction_pcg_iterates_match_oracle(bp, p, ncomp):
+    # the Chronopoulos-Gear recurrences against the oracle's standard PCG:
+    # the same iterates up to rounding
+    c = Case(bp, p, *grid_for(p), seed=23, ncomp=ncomp)
+    try:
+        c.op.set_cg_variant(True)
+        which = MASS if bp == 1 else STIFF
+        mask = (1 - c.mesh.boundary) if bp >= 3 else np.ones(c.disc.nglobal)
+        b = c.vec(5) * (mask[:, None] if ncomp > 1 else mask)
+        rec = []
+        A = lambda v: c.disc.apply(which, v, masked=bp >= 3)
+        pcg(A, b, c.disc.jacobi_inverse(which, masked=bp >= 3), maxit=8, fixed_iters=True,
+            record=rec)
+        for k in (1, 2, 5, 8):
+            x, st = c.op.pcg_solve(dev(b), which=which, maxit=k, fixed_iters=True)
+            assert st["iters"] == k
+            assert rel(host(x), rec[k - 1]) <= TOL, (k, rel(host(x), rec[k - 1]))
+        # tolerance mode: the same stopping iteration (+-1) and solution as standard
+        xs, sts = c.op.pcg_solve(dev(b), which=which, rtol=1e-10, maxit=5000)
+        c.op.set_cg_variant(False)
+        x0, st0 = c.op.pcg_solve(dev(b), which=which, rtol=1e-10, maxit=5000)
+        assert sts["converged"] and abs(sts["iters"] - st0["iters"]) <= 1
+        assert rel(host(xs), host(x0)) <= 1e-9
+    finally:
+        c.close()
+
+
 def test_pcg_iterates_match_oracle_config1():
     c = Case(5, 3, 4, 4, 4, seed=0)
     try:
