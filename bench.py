@@ -479,6 +479,8 @@ def main():
     ap.add_argument("--sweep-bp", type=int, nargs="+", default=[1, 3], help="sweep13: which BPs")
     ap.add_argument("--sweep-n", type=int, nargs="+", default=list(range(1, 9)),
                     help="sweep13: which orders N")
+    ap.add_argument("--cg", default="standard", choices=["standard", "single-reduction"],
+                    help="PCG recurrences of the bp5 workload and its sweep")
     ap.add_argument("--bk", type=int, default=5, choices=[1, 3, 5],
                     help="bk workload: which bake-off kernel")
     ap.add_argument("--workload", default="bp5",
@@ -514,6 +516,7 @@ def main():
     op, b, info = build_problem(bp, N, k)
     log(f"setup done in {time.perf_counter() - t0:.1f} s: n={info['n']} unique={info['n_unique']}")
     op.set_option(BP_OPT_TIME_APPLY, 1)
+    op.set_cg_variant(args.cg == "single-reduction")
     wall, st = time_solve(op, b, args.steps, args.warmup)
     if args.fp32_iters:
         op.close()
@@ -547,6 +550,7 @@ def main():
         "config": {"workload": f"BP5 scalar Poisson, GLL q=N+1, N={N}, E={info['grid'][0]}x"
                                f"{info['grid'][1]}x{info['grid'][2]}, Jacobi-PCG fixed "
                                f"{args.steps} iterations",
+                   "cg": args.cg,
                    "N": N, "E": E, "n": n, "n_unique": info["n_unique"]},
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": model.HBM_PEAK_GBS, "unit": "GB/s",
@@ -567,6 +571,7 @@ def main():
         pts = [(n, value)]
         for kk in range(lo, min(hi, k - 1) + 1):
             o2, b2, inf2 = build_problem(bp, N, kk)
+            o2.set_cg_variant(args.cg == "single-reduction")
             w2, st2 = time_solve(o2, b2, 100, 10)
             r = 100 * inf2["n"] / w2
             pts.append((inf2["n"], r))
