@@ -43,12 +43,14 @@ def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0, fp32: 
     xi, _ = B.rule(N + 1, B.GLL)
     mesh = synth.brick_mesh(ex, ey, ez, N, xi, seed=0)
     dirich = mesh.boundary if bp >= 3 else None
+    t0 = time.perf_counter()
     op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp,
                     fp32=fp32)
+    t_op = time.perf_counter() - t0
     b = synth.rhs_uniform(mesh.nglobal, seed, ncomp=ncomp, dirichlet=dirich)
     bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()     # component-major
     info = {"E": ex * ey * ez, "grid": [ex, ey, ez], "n": N ** 3 * ex * ey * ez,
-            "n_unique": int(mesh.nglobal)}
+            "n_unique": int(mesh.nglobal), "operator_setup_s": t_op}
     del mesh
     return op, bd, info
 
@@ -514,7 +516,8 @@ def main():
     log(f"setup BP{bp} N={N} E=2^{k}")
     t0 = time.perf_counter()
     op, b, info = build_problem(bp, N, k)
-    log(f"setup done in {time.perf_counter() - t0:.1f} s: n={info['n']} unique={info['n_unique']}")
+    log(f"setup done in {time.perf_counter() - t0:.1f} s (operator {info['operator_setup_s']:.2f} s)"
+        f": n={info['n']} unique={info['n_unique']}")
     op.set_option(BP_OPT_TIME_APPLY, 1)
     op.set_cg_variant(args.cg == "single-reduction")
     wall, st = time_solve(op, b, args.steps, args.warmup)

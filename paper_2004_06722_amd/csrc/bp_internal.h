@@ -38,13 +38,6 @@ struct Basis {
 };
 Basis make_basis(int p, int q, int quad);
 
-// Geometric factors of eq. (gij) and B~ of eq. (mass) for every element,
-// computed with `nthreads` host threads. G [E][6][q^3], Bt [E][q^3].
-// Returns -1 on success, else the first element with Jacobian <= 0 (or
-// non-finite) at some quadrature point.
-int64_t geometric_factors(const Basis &b, int64_t nelem, const double *node_xyz,
-                          double *G, double *Bt, int nthreads);
-
 // ---- device-side scalars of the CG iteration --------------------------------
 constexpr int kMaxComp = 8;
 constexpr int kMaxTimedApplies = 4096;

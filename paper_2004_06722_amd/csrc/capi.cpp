@@ -5,7 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <thread>
+#include <climits>
 #include <vector>
 
 #include "bp_internal.h"
@@ -80,18 +80,14 @@ void release(bp_op op) {
   delete op;
 }
 
-int host_threads() {
-  unsigned h = std::thread::hardware_concurrency();
-  return (int)std::max(1u, std::min(h, 32u));
-}
-
-// Upload basis J | D | Dq (FP64 and optional FP32 copies).
+// Upload basis J | D | Dq | 1D quadrature weights (FP64 and optional FP32 copies).
 int upload_basis(bp_op op, hipStream_t s) {
   const Basis &b = op->basis;
   std::vector<double> all;
   all.insert(all.end(), b.J.begin(), b.J.end());
   all.insert(all.end(), b.D.begin(), b.D.end());
   all.insert(all.end(), b.Dq.begin(), b.Dq.end());
+  all.insert(all.end(), b.rho.begin(), b.rho.end());
   int rc = dmalloc(&op->basis_d, all.size());
   if (rc) return rc;
   BP_HIP(hipMemcpyAsync(op->basis_d, all.data(), all.size() * sizeof(double),
@@ -465,16 +461,6 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
     return set_error(BP_ERR_HIP, "bp_setup: no HIP device");
   }
 
-  // geometric factors on the host
-  std::vector<double> G((size_t)(nelem * 6 * nq)), Bt((size_t)(nelem * nq));
-  const int64_t bad = geometric_factors(op->basis, nelem, node_xyz, G.data(), Bt.data(),
-                                        host_threads());
-  if (bad >= 0) {
-    release(op);
-    return set_error(BP_ERR_MESH, "bp_setup: non-positive Jacobian in element " +
-                                      std::to_string(bad));
-  }
-
   int rc = BP_OK;
 #define TRY(x)          \
   do {                  \
@@ -495,13 +481,39 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
 
   const int64_t nv = nglobal * ncomp;
   TRY(dmalloc(&op->idx, idx.size()));
-  TRY(dmalloc(&op->G, G.size()));
-  TRY(dmalloc(&op->Bt, Bt.size()));
   TRYHIP(hipMemcpyAsync(op->idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  TRYHIP(hipMemcpyAsync(op->G, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  TRYHIP(hipMemcpyAsync(op->Bt, Bt.data(), Bt.size() * sizeof(double), hipMemcpyHostToDevice, s));
   TRYHIP(hipStreamSynchronize(s));
   TRY(upload_basis(op, s));
+
+  // geometric factors of eq. (gij) and B~ of eq. (mass), computed on the device
+  // from the node coordinates (held only for this call)
+  const int64_t ng = nelem * 6 * nq, nb = nelem * nq;
+  TRY(dmalloc(&op->G, ng));
+  TRY(dmalloc(&op->Bt, nb));
+  {
+    double *X = nullptr;
+    int *bad = nullptr;
+    const int big = INT_MAX;
+    int bad_host = INT_MAX;
+    rc = dmalloc(&X, nelem * n3 * 3);
+    if (!rc) rc = dmalloc(&bad, 1);
+    if (!rc && hipMemcpyAsync(X, node_xyz, (size_t)(nelem * n3 * 3) * sizeof(double),
+                              hipMemcpyHostToDevice, s) != hipSuccess)
+      rc = set_error(BP_ERR_HIP, "bp_setup: coordinate upload failed");
+    if (!rc && hipMemcpyAsync(bad, &big, sizeof(int), hipMemcpyHostToDevice, s) != hipSuccess)
+      rc = set_error(BP_ERR_HIP, "bp_setup: flag upload failed");
+    if (!rc) rc = launch_geometry(op, X, op->G, op->Bt, bad, s);
+    if (!rc && (hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess))
+      rc = set_error(BP_ERR_HIP, "bp_setup: geometric factors failed");
+    dfree(X);
+    dfree(bad);
+    if (!rc && bad_host != INT_MAX)
+      rc = set_error(BP_ERR_MESH, "bp_setup: non-positive Jacobian in element " +
+                                      std::to_string(bad_host));
+    TRY(rc);
+  }
   TRY(dmalloc(&op->r, nv));
   TRY(dmalloc(&op->pv, nv));
   TRY(dmalloc(&op->w, nv));
@@ -515,13 +527,11 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRYHIP(hipEventCreate(&op->ev0));
   TRYHIP(hipEventCreate(&op->ev1));
   if (op->fp32) {
-    std::vector<float> f(G.begin(), G.end());
-    TRY(dmalloc(&op->G32, f.size()));
-    TRYHIP(hipMemcpyAsync(op->G32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
-    TRYHIP(hipStreamSynchronize(s));
-    std::vector<float> fb(Bt.begin(), Bt.end());
-    TRY(dmalloc(&op->Bt32, fb.size()));
-    TRYHIP(hipMemcpyAsync(op->Bt32, fb.data(), fb.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    TRY(dmalloc(&op->G32, ng));
+    TRY(dmalloc(&op->Bt32, nb));
+    to_f32(op->G, op->G32, ng, s);
+    to_f32(op->Bt, op->Bt32, nb, s);
+    TRYHIP(hipGetLastError());
     TRYHIP(hipStreamSynchronize(s));
     TRY(dmalloc(&op->r32, nv));
     TRY(dmalloc(&op->p32, nv));

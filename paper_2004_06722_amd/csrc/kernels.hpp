@@ -569,6 +569,103 @@ __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
 }
 
 // ---------------------------------------------------------------------------
+// Geometric factors of eq. (gij) and B~ of eq. (mass) at set-up, one
+// work-group per element (grid-stride over elements). The element's node
+// coordinates are interpolated to the quadrature points with J^ along i, j
+// and k (nothing to do with collocated GLL points), the derivatives
+// dx_l/dr_m are taken there with D~ (exact: x is a polynomial of degree p < q
+// in each variable), and the inverse Jacobian comes from the cofactor matrix:
+// G_mm' = sum_l cof_lm cof_lm' w / det and B~ = det w, w the product of the
+// 1D weights. `bad` receives the smallest element index with det <= 0 (or
+// non-finite) at some point. Dynamic LDS: two regions, A (coordinates, then
+// the j-pass) and B (the i-pass, then the coordinates at the points).
+// basis: J^ (q x p1) | D^ (q x p1) | D~ (q x q) | 1D weights (q).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_geometry(int64_t nelem, int p1, int q, int colloc,
+                                                  const double *__restrict__ X,
+                                                  const double *__restrict__ basis,
+                                                  double *__restrict__ G,
+                                                  double *__restrict__ Bt, int *__restrict__ bad) {
+  extern __shared__ double gsm[];
+  const int n3 = p1 * p1 * p1, nq = q * q * q;
+  const int ra = 3 * (n3 > p1 * q * q ? n3 : p1 * q * q);
+  double *A = gsm, *B = gsm + ra;
+  const double *J = basis, *Dq = basis + 2 * q * p1, *rho = basis + 2 * q * p1 + q * q;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
+    for (int x = t; x < 3 * n3; x += nt) A[x] = X[e * 3 * n3 + x];
+    __syncthreads();
+    const double *Xq = A;
+    if (!colloc) {
+      // along i: B[k][j][a][l] = sum_i J^[a][i] X[k][j][i][l]
+      for (int x = t; x < 3 * p1 * p1 * q; x += nt) {
+        const int l = x % 3, a = (x / 3) % q, kj = x / (3 * q);
+        double sum = 0.0;
+        for (int i = 0; i < p1; ++i) sum += J[a * p1 + i] * A[(kj * p1 + i) * 3 + l];
+        B[x] = sum;
+      }
+      __syncthreads();
+      // along j: A[k][b][a][l] = sum_j J^[b][j] B[k][j][a][l]
+      for (int x = t; x < 3 * p1 * q * q; x += nt) {
+        const int l = x % 3, a = (x / 3) % q, bq = (x / (3 * q)) % q, k = x / (3 * q * q);
+        double sum = 0.0;
+        for (int j = 0; j < p1; ++j) sum += J[bq * p1 + j] * B[((k * p1 + j) * q + a) * 3 + l];
+        A[x] = sum;
+      }
+      __syncthreads();
+      // along k: B[c][b][a][l] = sum_k J^[c][k] A[k][b][a][l]
+      for (int x = t; x < 3 * nq; x += nt) {
+        const int l = x % 3, ba = (x / 3) % (q * q), c = x / (3 * q * q);
+        double sum = 0.0;
+        for (int k = 0; k < p1; ++k) sum += J[c * p1 + k] * A[(k * q * q + ba) * 3 + l];
+        B[x] = sum;
+      }
+      __syncthreads();
+      Xq = B;
+    }
+    for (int n = t; n < nq; n += nt) {
+      const int a = n % q, bq = (n / q) % q, c = n / (q * q);
+      double M[3][3];  // M[l][m] = dx_l / dr_m
+      for (int l = 0; l < 3; ++l) {
+        double dr = 0.0, ds = 0.0, dt = 0.0;
+        for (int m = 0; m < q; ++m) {
+          dr += Dq[a * q + m] * Xq[((c * q + bq) * q + m) * 3 + l];
+          ds += Dq[bq * q + m] * Xq[((c * q + m) * q + a) * 3 + l];
+          dt += Dq[c * q + m] * Xq[((m * q + bq) * q + a) * 3 + l];
+        }
+        M[l][0] = dr;
+        M[l][1] = ds;
+        M[l][2] = dt;
+      }
+      double cof[3][3];
+      cof[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+      cof[0][1] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+      cof[0][2] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+      cof[1][0] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+      cof[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+      cof[1][2] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+      cof[2][0] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+      cof[2][1] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+      cof[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+      const double det = M[0][0] * cof[0][0] + M[0][1] * cof[0][1] + M[0][2] * cof[0][2];
+      if (!(det > 0.0) || !isfinite(det)) atomicMin(bad, (int)e);
+      const double wq = rho[a] * rho[bq] * rho[c];
+      const double sc = wq / det;
+      int comp = 0;
+      for (int m = 0; m < 3; ++m)
+        for (int mp = m; mp < 3; ++mp) {
+          double g = 0.0;
+          for (int l = 0; l < 3; ++l) g += cof[l][m] * cof[l][mp];
+          G[(e * 6 + comp) * nq + n] = g * sc;
+          ++comp;
+        }
+      Bt[e * nq + n] = det * wq;
+    }
+    __syncthreads();  // the regions are rewritten for the next element
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Diagonal of the assembled operator (Jacobi preconditioner, section 3).
 // diag(A^e)_{ijk} = sum_{mm'} sum_{abc} G_mm'(a,b,c) phi_m phi_m' with
 // phi_1 = D[a][i] J[b][j] J[c][k], phi_2 = J[a][i] D[b][j] J[c][k],

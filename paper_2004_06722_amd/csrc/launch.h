@@ -21,6 +21,10 @@ int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w,
 int launch_apply_local(const bp_op_s *op, int which, bool f32, const void *uL, void *wL,
                        hipStream_t s);
 int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_t s);
+// G [E][6][q^3] and Bt [E][q^3] from the node coordinates X [E][p1^3][3] (device);
+// *bad (device, preset to INT_MAX) gets the smallest element with det J <= 0
+int launch_geometry(const bp_op_s *op, const double *X, double *G, double *Bt, int *bad,
+                    hipStream_t s);
 int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, double *g,
                       hipStream_t s);
 

@@ -193,6 +193,18 @@ int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_
   return BP_OK;
 }
 
+int launch_geometry(const bp_op_s *op, const double *X, double *G, double *Bt, int *bad,
+                    hipStream_t s) {
+  const int p1 = op->p1, q = op->q;
+  const size_t n3 = (size_t)p1 * p1 * p1, nq = (size_t)q * q * q;
+  const size_t ra = 3 * std::max(n3, (size_t)p1 * q * q), rb = 3 * std::max((size_t)p1 * p1 * q, nq);
+  const int64_t grid = op->nelem < 65536 ? op->nelem : 65536;
+  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(256), (ra + rb) * sizeof(double), s, op->nelem,
+                     p1, q, op->colloc ? 1 : 0, X, op->basis_d, G, Bt, bad);
+  BP_HIP(hipGetLastError());
+  return BP_OK;
+}
+
 int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, double *g,
                       hipStream_t s) {
   if (!op->colloc) return set_error(BP_ERR_ARG, "bp_grad_kappa: only collocated GLL operators");

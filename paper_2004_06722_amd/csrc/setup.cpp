@@ -1,9 +1,7 @@
-// Host-side setup of the bake-off operators: 1D rules, Lagrange matrices and
-// the geometric factors (section 3: all geometric data are precomputed).
+// Host-side setup of the bake-off operators: 1D rules and Lagrange matrices
+// (the geometric factors of section 3 are computed on the device at set-up).
 #include <algorithm>
-#include <atomic>
 #include <cmath>
-#include <thread>
 
 #include "bp_internal.h"
 
@@ -186,133 +184,6 @@ Basis make_basis(int p, int q, int quad) {
   lagrange_deriv(b.p1, b.xi.data(), q, b.eta.data(), b.D.data());
   lagrange_deriv(q, b.eta.data(), q, b.eta.data(), b.Dq.data());
   return b;
-}
-
-// Geometric factors of one element. For collocated GLL the derivatives of the
-// coordinates are taken with D^ directly at the nodes; otherwise the nodes are
-// first interpolated to the quadrature points (J^ in each direction) and then
-// differentiated there with the q x q matrix Dq (exact: x is a polynomial of
-// degree p < q in each variable).
-static bool element_factors(const Basis &b, const double *X, double *G, double *Bt,
-                            std::vector<double> &s1, std::vector<double> &s2,
-                            std::vector<double> &Xq) {
-  const int p1 = b.p1, q = b.q;
-  const int nq = q * q * q;
-  // Xq[c][b][a][l]: coordinate l at quadrature point (a, b, c)
-  if (b.colloc) {
-    for (int n = 0; n < nq; ++n)
-      for (int l = 0; l < 3; ++l) Xq[n * 3 + l] = X[n * 3 + l];
-  } else {
-    // along i: s1[k][j][a][l]
-    for (int k = 0; k < p1; ++k)
-      for (int j = 0; j < p1; ++j)
-        for (int a = 0; a < q; ++a)
-          for (int l = 0; l < 3; ++l) {
-            double s = 0.0;
-            for (int i = 0; i < p1; ++i)
-              s += b.J[a * p1 + i] * X[((k * p1 + j) * p1 + i) * 3 + l];
-            s1[((k * p1 + j) * q + a) * 3 + l] = s;
-          }
-    // along j: s2[k][bb][a][l]
-    for (int k = 0; k < p1; ++k)
-      for (int bb = 0; bb < q; ++bb)
-        for (int a = 0; a < q; ++a)
-          for (int l = 0; l < 3; ++l) {
-            double s = 0.0;
-            for (int j = 0; j < p1; ++j)
-              s += b.J[bb * p1 + j] * s1[((k * p1 + j) * q + a) * 3 + l];
-            s2[((k * q + bb) * q + a) * 3 + l] = s;
-          }
-    // along k
-    for (int c = 0; c < q; ++c)
-      for (int bb = 0; bb < q; ++bb)
-        for (int a = 0; a < q; ++a)
-          for (int l = 0; l < 3; ++l) {
-            double s = 0.0;
-            for (int k = 0; k < p1; ++k)
-              s += b.J[c * p1 + k] * s2[((k * q + bb) * q + a) * 3 + l];
-            Xq[((c * q + bb) * q + a) * 3 + l] = s;
-          }
-  }
-  const double *Dm = b.colloc ? b.D.data() : b.Dq.data();  // q x q in both cases
-  bool ok = true;
-  for (int c = 0; c < q; ++c)
-    for (int bb = 0; bb < q; ++bb)
-      for (int a = 0; a < q; ++a) {
-        double M[3][3];  // M[l][m] = dx_l / dr_m
-        for (int l = 0; l < 3; ++l) {
-          double dr = 0.0, ds = 0.0, dt = 0.0;
-          for (int m = 0; m < q; ++m) {
-            dr += Dm[a * q + m] * Xq[((c * q + bb) * q + m) * 3 + l];
-            ds += Dm[bb * q + m] * Xq[((c * q + m) * q + a) * 3 + l];
-            dt += Dm[c * q + m] * Xq[((m * q + bb) * q + a) * 3 + l];
-          }
-          M[l][0] = dr;
-          M[l][1] = ds;
-          M[l][2] = dt;
-        }
-        // cofactor matrix: inverse = cof^T / det, (dr_m/dx_l) = cof[l][m] / det
-        double cof[3][3];
-        cof[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
-        cof[0][1] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
-        cof[0][2] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
-        cof[1][0] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
-        cof[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
-        cof[1][2] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
-        cof[2][0] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
-        cof[2][1] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
-        cof[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
-        const double det = M[0][0] * cof[0][0] + M[0][1] * cof[0][1] + M[0][2] * cof[0][2];
-        if (!(det > 0.0) || !std::isfinite(det)) ok = false;
-        const double wq = b.rho[a] * b.rho[bb] * b.rho[c];
-        // G_mm' = sum_l (dr_m/dx_l)(dr_m'/dx_l) det w = sum_l cof[l][m] cof[l][m'] w / det
-        const double s = wq / det;
-        const int n = (c * q + bb) * q + a;
-        int comp = 0;
-        for (int m = 0; m < 3; ++m)
-          for (int mp = m; mp < 3; ++mp) {
-            double g = 0.0;
-            for (int l = 0; l < 3; ++l) g += cof[l][m] * cof[l][mp];
-            G[(size_t)comp * nq + n] = g * s;
-            ++comp;
-          }
-        Bt[n] = det * wq;
-      }
-  return ok;
-}
-
-int64_t geometric_factors(const Basis &b, int64_t nelem, const double *node_xyz,
-                          double *G, double *Bt, int nthreads) {
-  const int p1 = b.p1, q = b.q;
-  const int64_t n3 = (int64_t)p1 * p1 * p1, nq = (int64_t)q * q * q;
-  std::atomic<int64_t> bad(INT64_MAX);
-  std::atomic<int64_t> next(0);
-  const int64_t chunk = 256;
-  auto work = [&]() {
-    std::vector<double> s1((size_t)p1 * p1 * q * 3), s2((size_t)p1 * q * q * 3),
-        Xq((size_t)nq * 3);
-    for (;;) {
-      int64_t e0 = next.fetch_add(chunk);
-      if (e0 >= nelem) break;
-      int64_t e1 = std::min(nelem, e0 + chunk);
-      for (int64_t e = e0; e < e1; ++e) {
-        bool ok = element_factors(b, node_xyz + e * n3 * 3, G + e * 6 * nq, Bt + e * nq,
-                                  s1, s2, Xq);
-        if (!ok) {
-          int64_t cur = bad.load();
-          while (e < cur && !bad.compare_exchange_weak(cur, e)) {
-          }
-        }
-      }
-    }
-  };
-  nthreads = std::max(1, std::min<int>(nthreads, (int)((nelem + chunk - 1) / chunk)));
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
-  work();
-  for (auto &t : pool) t.join();
-  int64_t r = bad.load();
-  return r == INT64_MAX ? -1 : r;
 }
 
 }  // namespace bp

@@ -349,6 +349,17 @@ def test_errors_are_reported():
         B.Operator(3, 4, B.GLL, m.elem_dofs, xyz, m.nglobal)
     with pytest.raises(BpError, match="BP_ERR_ARG"):
         B.Operator(9, 10, B.GLL, np.zeros((1, 1000), np.int64), np.zeros((1, 1000, 3)), 1000)
+    # the device set-up reports the smallest bad element, also on GL points
+    m4 = synth.brick_mesh(4, 2, 1, 3, xi, seed=None)
+    xyz = m4.node_xyz.copy()
+    for e in (6, 3):
+        xyz[e, :, 1] = -xyz[e, :, 1]
+    with pytest.raises(BpError, match="element 3$"):
+        B.Operator(3, 5, B.GL, m4.elem_dofs, xyz, m4.nglobal)
+    xyz = m4.node_xyz.copy()
+    xyz[7, 0, 2] = np.inf
+    with pytest.raises(BpError, match="element 7$"):
+        B.Operator(3, 4, B.GLL, m4.elem_dofs, xyz, m4.nglobal)
     op = B.Operator(3, 4, B.GLL, m.elem_dofs, m.node_xyz, m.nglobal, m.boundary)
     try:
         b = np.zeros(m.nglobal)
