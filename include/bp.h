@@ -117,8 +117,9 @@ int bp_set_coeff(bp_op op, const double *kappa_q, void *stream);
  *   beta_q: device double [nelem][q^3] (beta at the quadrature points, read
  *     during the call), or NULL for the constant `beta`.
  *   beta = 0 with beta_q = NULL removes the term (BP_HELM then equals
- *   BP_STIFF). With GLL quadrature the term is fused into the stiffness kernel
- *   (B_beta is diagonal); with GL points it is a second kernel adding into w.
+ *   BP_STIFF). The term is fused into the stiffness kernel: with GLL
+ *   quadrature B_beta is diagonal; with GL points the kernel interpolates u
+ *   to the points once more.
  * Errors: BP_ERR_ARG (non-finite beta), BP_ERR_OOM, BP_ERR_HIP.
  */
 int bp_set_helmholtz(bp_op op, double beta, const double *beta_q, void *stream);

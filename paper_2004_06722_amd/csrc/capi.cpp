@@ -80,7 +80,24 @@ void release(bp_op op) {
   delete op;
 }
 
-// Upload basis J | D | Dq | 1D quadrature weights (FP64 and optional FP32 copies).
+// Even-odd tables of the q x p1 matrix M with M[q-1-a][p1-1-i] = sign M[a][i]
+// (symmetric point sets): for a < (q+1)/2, (M[a][i] + M[a][p1-1-i]) / 2 and
+// (M[a][i] - M[a][p1-1-i]) / 2 for i < p1/2, then M[a][p1/2] for odd p1. M is
+// first symmetrised, so that entries zero by symmetry are exactly zero.
+void even_odd_table(const std::vector<double> &M, int q, int p1, int sign,
+                    std::vector<double> &out) {
+  auto ms = [&](int a, int i) {
+    return 0.5 * (M[(size_t)a * p1 + i] + sign * M[(size_t)(q - 1 - a) * p1 + (p1 - 1 - i)]);
+  };
+  for (int a = 0; a < (q + 1) / 2; ++a) {
+    for (int i = 0; i < p1 / 2; ++i) out.push_back(0.5 * (ms(a, i) + ms(a, p1 - 1 - i)));
+    for (int i = 0; i < p1 / 2; ++i) out.push_back(0.5 * (ms(a, i) - ms(a, p1 - 1 - i)));
+    if (p1 & 1) out.push_back(ms(a, p1 / 2));
+  }
+}
+
+// Upload basis J | D | Dq | 1D quadrature weights | even-odd tables of J and D
+// (FP64 and optional FP32 copies).
 int upload_basis(bp_op op, hipStream_t s) {
   const Basis &b = op->basis;
   std::vector<double> all;
@@ -88,6 +105,8 @@ int upload_basis(bp_op op, hipStream_t s) {
   all.insert(all.end(), b.D.begin(), b.D.end());
   all.insert(all.end(), b.Dq.begin(), b.Dq.end());
   all.insert(all.end(), b.rho.begin(), b.rho.end());
+  even_odd_table(b.J, b.q, b.p1, 1, all);
+  even_odd_table(b.D, b.q, b.p1, -1, all);
   int rc = dmalloc(&op->basis_d, all.size());
   if (rc) return rc;
   BP_HIP(hipMemcpyAsync(op->basis_d, all.data(), all.size() * sizeof(double),
@@ -572,7 +591,7 @@ int bp_set_coeff(bp_op op, const double *kappa_q, void *stream) {
         if (rc) return rc;
       }
     }
-    scale_geometry(op->G, kappa_q, op->Gk, op->Gk32, op->nelem, nq, s);
+    scale_geometry(op->G, kappa_q, op->Gk, op->Gk32, op->colloc ? 0 : op->q, op->nelem, nq, s);
     BP_HIP(hipGetLastError());
     op->kappa_set = true;
   }
@@ -600,10 +619,10 @@ int bp_set_helmholtz(bp_op op, double beta, const double *beta_q, void *stream) 
         if (rc) return rc;
       }
     }
-    scale_mass(op->Bt, beta_q, beta, op->Bb, op->Bb32, count, s);
+    scale_mass(op->Bt, beta_q, beta, op->Bb, op->Bb32, op->q * op->q * op->q,
+               op->colloc ? 0 : op->q, count, s);
     BP_HIP(hipGetLastError());
   }
-  // (the partial-sum buffer is sized at setup for both GL launches of BP_HELM)
   op->dinv_valid[2] = false;
   return BP_OK;
 }

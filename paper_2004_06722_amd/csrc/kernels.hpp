@@ -293,279 +293,405 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
 
 // ---------------------------------------------------------------------------
 // BK1-BK4: Gauss-Legendre quadrature with q = p1 + 1 points per direction.
-// Thread (a, b) of a q x q plane owns the quadrature column (a, b, .) and
-// keeps it in registers, so every contraction along t is register-only; the
-// r and s contractions go through padded LDS tiles. Lanes with a, b < p1
-// also own node column (a, b, .) for the gather and the scatter.
-// Stiffness (section 5, eq. (gradr2)-(gradt2) with shared partial sums):
-//   u_t = J^_t u, then J^_s and D^_s of it, then J^_r and D^_r of those give
-//   the interpolated values x, u_r and u_s; u_t = D~_t x along the column,
-// where D^ = D~ J^ is the derivative of the nodal basis at the Gauss points.
-// Then v = G (u_r, u_s, u_t) and the transposed chain back to the nodes.
-// Mass: J^ along t, s, r, then B~, then J^T along r, s, t.
-// Several elements share a work-group of up to 256 threads so that few lanes
-// idle; the G (or B~) column and the gather map are requested at entry. The
-// local energy is accumulated at the quadrature points. One component per
-// launch (u and w point at component c0): keeping G live across a loop over
-// components would cost the registers that the later stages reuse. With
-// LOCAL the result is stored per element (added to w when accum is set).
+// Every 1D contraction is done by a thread that owns a whole pencil of the
+// element (all entries along one direction) in registers, so each value read
+// from LDS feeds a full row of outputs, and the contraction uses the even-odd
+// splitting of the appendix on even-odd decompositions: the GLL nodes and the
+// Gauss points are both symmetric about 0, so J^ is centro-symmetric and D^
+// centro-antisymmetric, and each pair of mirrored outputs costs one pass over
+// half the (folded) inputs. Stages of the stiffness operator:
+//   1 column (i, j) along t: A = J^_t u, A' = D^_t u       -> LDS [j][c][i]
+//   2 pencil (i, c) along s: B = J^_s A, C = D^_s A, B' = J^_s A'
+//                                                          -> LDS [b][c][i]
+//   3 pencil (b, c) along r: u_r = D^_r B, u_s = J^_r C, u_t = J^_r B',
+//     v = G (u_r, u_s, u_t) (eq. (gij)), then P = D^T_r v_r, R = J^T_r v_s,
+//     T = J^T_r v_t, all in registers                      -> LDS (in place)
+//   4 pencil (i, c) along s: S1 = J^T_s P + D^T_s R, S2 = J^T_s T
+//                                                          -> LDS (in place)
+//   5 column (i, j) along t: w = J^T_t S1 + D^T_t S2, scatter-added.
+// The mass operator runs the J^ chains only with v = B~ x (eq. (mass)); the
+// Helmholtz operator (eq. (hm2)) runs both, adding J^T_r (beta B~ x) to P.
+// The quadrature data of these operators (G, B~) are stored with the point
+// index reversed, [a][b][c] with c fastest, so that the stage-3 pencils,
+// adjacent lanes along (b, c), read them coalesced; G and the gather map are
+// requested at entry. One component per launch (u and w point at component
+// c0). With LOCAL the result is stored per element.
 // ---------------------------------------------------------------------------
-// Scheduling fence between the quadrature levels of a stage: without it the
-// scheduler issues the LDS reads of every level at once and the lane runs out
-// of registers (the values already loaded, such as basis rows, stay live).
-__device__ __forceinline__ void level_fence() { __builtin_amdgcn_sched_barrier(0); }
+enum GLMode { kGLMass = 0, kGLStiff = 1, kGLHelm = 2 };
 
-// Materialise a value where it is computed: the compiler may not sink its
-// arithmetic to a later use and keep all the loaded inputs live instead.
-__device__ __forceinline__ double pin(double v) {
-  __asm__ volatile("" : "+v"(v));
-  return v;
-}
-__device__ __forceinline__ float pin(float v) {
-  __asm__ volatile("" : "+v"(v));
-  return v;
+// Even-odd tables of an NO x NI matrix M with M[NO-1-a][NI-1-i] = S M[a][i]:
+// row a < (NO+1)/2 holds E[a][i] = (M[a][i] + M[a][NI-1-i]) / 2 and
+// O[a][i] = (M[a][i] - M[a][NI-1-i]) / 2 for i < NI/2, then M[a][NI/2] when
+// NI is odd. Then for a < NO/2, with e_i = x_i + x_{NI-1-i} and
+// o_i = x_i - x_{NI-1-i}: y_a = E e + O o (+ middle term), and
+// y_{NO-1-a} = S (E e - O o (+ middle term)).
+template <int NO, int NI>
+struct EvenOdd {
+  static constexpr int H = NI / 2, HO = NO / 2, ROWS = (NO + 1) / 2, SIZE = ROWS * NI;
+  static constexpr bool MI = (NI & 1) != 0, MO = (NO & 1) != 0;
+};
+
+// Folded input pencil: mirrored sums and differences, and the middle entry.
+template <int NI, typename T>
+struct Folded {
+  T e[NI / 2 > 0 ? NI / 2 : 1], o[NI / 2 > 0 ? NI / 2 : 1], m;
+};
+
+template <int NI, typename T>
+__device__ __forceinline__ Folded<NI, T> fold(const T (&x)[NI]) {
+  Folded<NI, T> f;
+#pragma unroll
+  for (int i = 0; i < NI / 2; ++i) {
+    f.e[i] = x[i] + x[NI - 1 - i];
+    f.o[i] = x[i] - x[NI - 1 - i];
+  }
+  f.m = (NI & 1) ? x[NI / 2] : T(0);
+  return f;
 }
 
-// VS: at q = 8 and q = 10 the stiffness kernel parks v_s in a fourth LDS
-// tile instead of registers (the register file would otherwise spill); the
-// larger LDS footprint then takes fewer elements per work-group.
-template <int Q, bool STIFF>
-struct QPlane {
-  static constexpr bool VS = STIFF && (Q == 8 || Q == 10);
-  static constexpr int NT = STIFF ? (VS ? 4 : 3) : 2;  // LDS tiles per element
-  static constexpr int N = Q * Q;
-  static constexpr int EPB = VS ? (Q == 8 ? 3 : 1) : (N >= 256 ? 1 : 256 / N);
-  static constexpr int USED = EPB * N;
+// Outputs a and NO-1-a of y = M x (only ya for the middle row of odd NO,
+// where one half is zero by symmetry).
+template <int NO, int NI, int S, typename T>
+__device__ __forceinline__ void eo_row(const T *__restrict__ tab, int a, const Folded<NI, T> &x,
+                                       T &ya, T &yb) {
+  using E = EvenOdd<NO, NI>;
+  const T *r = tab + a * NI;
+  const bool mid = E::MO && a == E::HO;
+  T ye = 0, yo = 0;
+  if (!mid || S > 0) {
+#pragma unroll
+    for (int i = 0; i < E::H; ++i) ye += r[i] * x.e[i];
+    if constexpr (E::MI) ye += r[2 * E::H] * x.m;
+  }
+  if (!mid || S < 0) {
+#pragma unroll
+    for (int i = 0; i < E::H; ++i) yo += r[E::H + i] * x.o[i];
+  }
+  ya = ye + yo;
+  yb = S > 0 ? ye - yo : yo - ye;
+}
+
+// z = M^T v accumulated input pair by input pair: p[i] = (z_i + z_{NI-1-i})/2,
+// m[i] = (z_i - z_{NI-1-i})/2, c = z_{NI/2} (odd NI).
+template <int NI, typename T>
+struct Unfold {
+  T p[NI / 2 > 0 ? NI / 2 : 1], m[NI / 2 > 0 ? NI / 2 : 1], c;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < NI / 2; ++i) p[i] = m[i] = T(0);
+    c = T(0);
+  }
+  // inputs a and NO-1-a (a < NO/2), or the middle input alone
+  template <int NO, int S>
+  __device__ __forceinline__ void add(const T *__restrict__ tab, int a, T va, T vb) {
+    using E = EvenOdd<NO, NI>;
+    const T *r = tab + a * NI;
+    const bool mid = E::MO && a == E::HO;
+    const T sp = mid ? va : (S > 0 ? va + vb : va - vb);
+    const T sm = mid ? va : (S > 0 ? va - vb : va + vb);
+    if (!mid || S > 0) {
+#pragma unroll
+      for (int i = 0; i < E::H; ++i) p[i] += r[i] * sp;
+      if constexpr (E::MI) c += r[2 * E::H] * sp;
+    }
+    if (!mid || S < 0) {
+#pragma unroll
+      for (int i = 0; i < E::H; ++i) m[i] += r[E::H + i] * sm;
+    }
+  }
+  __device__ __forceinline__ void get(T (&z)[NI]) const {
+#pragma unroll
+    for (int i = 0; i < NI / 2; ++i) {
+      z[i] = p[i] + m[i];
+      z[NI - 1 - i] = p[i] - m[i];
+    }
+    if constexpr ((NI & 1) != 0) z[NI / 2] = c;
+  }
+};
+
+// LDS layout and elements per work-group of the Gauss-Legendre kernels: up
+// to 256 threads (q^2 per element) and at most 80 KB of LDS per work-group,
+// so that two work-groups share a CU.
+constexpr int gl_row_stride(int p1) { return p1 | 1; }
+constexpr int gl_lds_per_elem(int p1, int q, int mode) {
+  return (mode == kGLMass ? 1 : 2) * p1 * q * p1 +
+         (mode == kGLMass ? 1 : 3) * q * q * gl_row_stride(p1);
+}
+constexpr int gl_epb(int p1, int q, int mode) {
+  const int by_threads = q * q >= 256 ? 1 : 256 / (q * q);
+  const int by_lds = (80 * 1024 - 1024) / (8 * gl_lds_per_elem(p1, q, mode));
+  const int e = by_threads < by_lds ? by_threads : by_lds;
+  return e < 1 ? 1 : e;
+}
+
+template <int P1, int Q, int MODE>
+struct GLPlane {
+  static constexpr int NA = MODE == kGLMass ? 1 : 2;  // tiles [j][c][i] per element
+  static constexpr int NB = MODE == kGLMass ? 1 : 3;  // tiles [b][c][i] per element
+  static constexpr int RS = gl_row_stride(P1);        // odd row stride of the B tiles
+  static constexpr int EPB = gl_epb(P1, Q, MODE);
+  static constexpr int USED = EPB * Q * Q;
   static constexpr int THREADS = ((USED + 63) / 64) * 64;
 };
 
-template <int P1, int Q, typename T, bool STIFF, bool LOCAL = false>
-__global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
+template <int P1, int Q, typename T, int MODE, bool LOCAL = false>
+__global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
-    const T *__restrict__ basis, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
-    int masked, int accum, double *__restrict__ part, const int *__restrict__ done) {
-  using PL = QPlane<Q, STIFF>;
+    const T *__restrict__ Bb, const T *__restrict__ basis, const T *__restrict__ u,
+    T *__restrict__ w, int ncomp, int c0, int masked, double *__restrict__ part,
+    const int *__restrict__ done) {
+  using PL = GLPlane<P1, Q, MODE>;
+  using EO = EvenOdd<Q, P1>;
+  constexpr bool STIFF = MODE != kGLMass, HELM = MODE == kGLHelm;
   constexpr int N3 = P1 * P1 * P1, NQ = Q * Q * Q, QQ = Q * Q;
-  constexpr int RP = Q + 1;       // tile row: q entries and one pad entry
-  constexpr int TS = QQ * RP;     // tile [c][b][0..RP)
   constexpr int NG = STIFF ? 6 : 1;
-  constexpr int NT = PL::NT;
-  static_assert(Q == P1 + 1, "interpolating kernel expects q = p1 + 1");
+  constexpr int LA = Q * P1;                // A tiles: [j][c][i]
+  constexpr int RS = PL::RS, LB = Q * RS;   // B tiles: [b][c][i], rows of RS
+  static_assert(Q == P1 + 1, "Gauss-Legendre kernel expects q = p1 + 1");
   if (done && *done) return;
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
-  // Lanes past the last plane act as column a = q of plane 0: their tile
-  // stores land in the pad entries, which are never read, so no store needs
-  // a guard. Columns a, b >= p1 of the node-indexed stages are written but
-  // not read either.
   const int slot = act ? t / QQ : 0;
-  const int a = act ? t % Q : Q;
-  const int b = act ? (t % QQ) / Q : 0;
-  const int ab = act ? t % QQ : 0;
-  const int at = a < Q ? a : Q - 1;         // row of the basis tables
-  const int ic = a < P1 ? a : P1 - 1;       // node index along r (clamped)
-  const int jc = b < P1 ? b : P1 - 1;       // node index along s (clamped)
+  const int l = act ? t % QQ : QQ;  // lane in the element's plane (QQ: no role)
   const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
   const bool live = act && e < nelem;
   const int64_t ec = live ? e : nelem - 1;  // element whose data the lane reads
+  // roles: column (i, j) along t; pencil (i, c) along s; pencil (b, c) along r
+  const bool col = l < P1 * P1;
+  const int ci = col ? l % P1 : 0, cj = col ? l / P1 : 0;
+  const bool spn = l < Q * P1;
+  const int rl = l < QQ ? l : 0;
+  const int rrow = (rl / Q) * LB + (rl % Q) * RS;  // the r-pencil's row in the B tiles
 
-  __shared__ T sJ[Q][P1];  // J^[a][i]
-  __shared__ T sD[Q][P1];  // D^[a][i]
-  __shared__ T tile[PL::EPB][NT][TS];
-  T *const A = tile[slot][0];
-  T *const B = tile[slot][1];
-  T *const C = tile[slot][STIFF ? 2 : 1];  // third tile (stiffness only)
-  T *const V = tile[slot][NT - 1];         // v_s: fourth tile with PL::VS, else B
-  const int row = b * RP;           // offset of the lane's row in a level
+  __shared__ T sA[PL::EPB][PL::NA][P1 * LA];
+  __shared__ T sB[PL::EPB][PL::NB][Q * LB];
+  T *const A0 = sA[slot][0];
+  T *const A1 = sA[slot][PL::NA - 1];
+  T *const B0 = sB[slot][0];
+  T *const B1 = sB[slot][STIFF ? 1 : 0];
+  T *const B2 = sB[slot][PL::NB - 1];
+  const T *tJ = basis + 2 * Q * P1 + QQ + Q;  // even-odd tables of J^, then of D^
+  const T *tD = tJ + EO::SIZE;
 
-  // one round trip: node column of the gather map, quadrature column of G / B~
+  // one round trip: node column of the gather map, the r-pencil's G / B~
   int gk[P1];
 #pragma unroll
   for (int k = 0; k < P1; ++k)
-    gk[k] = LOCAL ? (int)(ec * N3) + ic + P1 * (jc + P1 * k) : idx[ec * N3 + ic + P1 * (jc + P1 * k)];
+    gk[k] = LOCAL ? (int)(ec * N3) + ci + P1 * (cj + P1 * k)
+                  : idx[ec * N3 + ci + P1 * (cj + P1 * k)];
   T g[NG][Q];
-  const T *Ge = Gm + ec * NG * NQ + ab;
+  {
+    const T *Ge = Gm + ec * NG * NQ + rl;
 #pragma unroll
-  for (int c = 0; c < Q; ++c)
+    for (int a = 0; a < Q; ++a)
 #pragma unroll
-    for (int n = 0; n < NG; ++n) g[n][c] = __builtin_nontemporal_load(Ge + n * NQ + c * QQ);
-  // bit k of mb: node k of the column is gathered and scattered
-  unsigned mb = 0;
+      for (int n = 0; n < NG; ++n) g[n][a] = __builtin_nontemporal_load(Ge + n * NQ + a * QQ);
+  }
+  unsigned mb = 0;  // bit k: node k of the column is gathered and scattered
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
     const int v = gk[k];
-    if (live && a < P1 && b < P1 && (LOCAL || v >= 0 || !masked)) mb |= 1u << k;
+    if (live && col && (LOCAL || v >= 0 || !masked)) mb |= 1u << k;
     if (!LOCAL) gk[k] = v >= 0 ? v : -1 - v;
   }
-  for (int x = t; x < Q * P1; x += PL::THREADS) {
-    sJ[x / P1][x % P1] = basis[x];
-    sD[x / P1][x % P1] = basis[Q * P1 + x];
-  }
-  const T *Jg = basis;               // J^[c][k] at c * P1 + k (uniform reads)
-  const T *Dq = basis + 2 * Q * P1;  // D~[c][m] at c * Q + m
 
-  {
-    // gather; interpolate along t in registers: A[c][j][i] = sum_k J^[c][k] u(i, j, k)
+  // 1: gather, then along t
+  if (col) {
     T uk[P1];
 #pragma unroll
     for (int k = 0; k < P1; ++k) {
       const T v = u[gk[k]];
       uk[k] = (mb >> k & 1u) ? v : T(0);
     }
+    const Folded<P1, T> f = fold(uk);
+    T *a0 = A0 + cj * LA + ci;
+    T *a1 = A1 + cj * LA + ci;
 #pragma unroll
-    for (int c = 0; c < Q; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < P1; ++k) s += Jg[c * P1 + k] * uk[k];
-      A[(c * Q) * RP + row + a] = s;
-    }
-    __syncthreads();
-    // along s (lane (i, b)): B[c][b][i] = sum_j J^[b][j] A[c][j][i]; C with D^
-#pragma unroll
-    for (int c = 0; c < Q; ++c) {
-      T s0 = 0, s1 = 0;
-#pragma unroll
-      for (int j = 0; j < P1; ++j) {
-        const T v = A[(c * Q + j) * RP + a];
-        s0 += sJ[b][j] * v;
-        if constexpr (STIFF) s1 += sD[b][j] * v;
+    for (int c = 0; c < EO::ROWS; ++c) {
+      T ya, yb;
+      eo_row<Q, P1, 1>(tJ, c, f, ya, yb);
+      a0[c * P1] = ya;
+      if (c < EO::HO) a0[(Q - 1 - c) * P1] = yb;
+      if constexpr (STIFF) {
+        eo_row<Q, P1, -1>(tD, c, f, ya, yb);
+        a1[c * P1] = ya;
+        if (c < EO::HO) a1[(Q - 1 - c) * P1] = yb;
       }
-      B[(c * Q) * RP + row + a] = s0;
-      if constexpr (STIFF) C[(c * Q) * RP + row + a] = s1;
-      level_fence();
     }
-    __syncthreads();
-    // along r: the column's interpolated values x
-    T x[Q];
+  }
+  __syncthreads();
+  // 2: along s (pencil (i, c) = lane l: its column of the A tiles is l + j LA)
+  if (spn) {
+    const int ob = (l / P1) * RS + l % P1;  // (c, i) in the B tiles
+    T x[P1];
 #pragma unroll
-    for (int c = 0; c < Q; ++c) {
-      T s0 = 0;
+    for (int j = 0; j < P1; ++j) x[j] = A0[j * LA + l];
+    const Folded<P1, T> f = fold(x);
 #pragma unroll
-      for (int i = 0; i < P1; ++i) s0 += sJ[at][i] * B[(c * Q) * RP + row + i];
-      x[c] = pin(s0);
-      level_fence();
+    for (int b = 0; b < EO::ROWS; ++b) {
+      T ya, yb;
+      eo_row<Q, P1, 1>(tJ, b, f, ya, yb);
+      B0[b * LB + ob] = ya;
+      if (b < EO::HO) B0[(Q - 1 - b) * LB + ob] = yb;
+      if constexpr (STIFF) {
+        eo_row<Q, P1, -1>(tD, b, f, ya, yb);
+        B1[b * LB + ob] = ya;
+        if (b < EO::HO) B1[(Q - 1 - b) * LB + ob] = yb;
+      }
     }
-    double en = 0.0;
-    T S[Q];  // column after the transposed r and s contractions
     if constexpr (STIFF) {
-      // per level: u_r, u_s along r, u_t along the column, G, energy;
-      // v_r into A (free since the s stage), v_s and v_t kept for later
-      T vsk[Q], vtk[Q];
 #pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T r0 = 0, s0 = 0, ut = 0;
+      for (int j = 0; j < P1; ++j) x[j] = A1[j * LA + l];
+      const Folded<P1, T> f1 = fold(x);
 #pragma unroll
-        for (int i = 0; i < P1; ++i) {
-          r0 += sD[at][i] * B[(c * Q) * RP + row + i];
-          s0 += sJ[at][i] * C[(c * Q) * RP + row + i];
-        }
-#pragma unroll
-        for (int m = 0; m < Q; ++m) ut += Dq[c * Q + m] * x[m];
-        const T vr = g[0][c] * r0 + g[1][c] * s0 + g[2][c] * ut;
-        const T vs = g[1][c] * r0 + g[3][c] * s0 + g[4][c] * ut;
-        const T vt = g[2][c] * r0 + g[4][c] * s0 + g[5][c] * ut;
-        if (live) en += (double)r0 * (double)vr + (double)s0 * (double)vs + (double)ut * (double)vt;
-        A[(c * Q) * RP + row + a] = vr;
-        if constexpr (PL::VS)
-          V[(c * Q) * RP + row + a] = vs;
-        else
-          vsk[c] = pin(vs);
-        vtk[c] = pin(vt);
-        level_fence();
-      }
-      // z = D~^T v_t along the column (values-space part of the t term)
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T s0 = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) s0 += Dq[m * Q + c] * vtk[m];
-        x[c] = s0;
-      }
-      __syncthreads();  // B and C have been read
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        if constexpr (!PL::VS) B[(c * Q) * RP + row + a] = vsk[c];
-        C[(c * Q) * RP + row + a] = x[c];
-      }
-      __syncthreads();
-      // back along r (lane (i, b)): P = D^T v_r + J^T z, R = J^T v_s
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T s0 = 0, s1 = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) {
-          const int o = (c * Q) * RP + row + m;
-          s0 += sD[m][ic] * A[o] + sJ[m][ic] * C[o];
-          s1 += sJ[m][ic] * (PL::VS ? V[o] : B[o]);
-        }
-        vsk[c] = pin(s0);
-        vtk[c] = pin(s1);
-        level_fence();
-      }
-      __syncthreads();
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        A[(c * Q) * RP + row + a] = vsk[c];
-        B[(c * Q) * RP + row + a] = vtk[c];
-      }
-      __syncthreads();
-      // back along s (lane (i, j)): S = J^T P + D^T R
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T s0 = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) {
-          const int o = (c * Q + m) * RP + ic;
-          s0 += sJ[m][jc] * A[o] + sD[m][jc] * B[o];
-        }
-        S[c] = pin(s0);
-        level_fence();
-      }
-    } else {
-      // B~ at the points, energy; values into A (free since the s stage)
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        const T v = g[0][c] * x[c];
-        if (live) en += (double)x[c] * (double)v;
-        A[(c * Q) * RP + row + a] = v;
-      }
-      __syncthreads();
-      // back along r (lane (i, b)) into B (read before the last barrier)
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T s0 = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) s0 += sJ[m][ic] * A[(c * Q) * RP + row + m];
-        B[(c * Q) * RP + row + a] = s0;
-        level_fence();
-      }
-      __syncthreads();
-      // back along s (lane (i, j))
-#pragma unroll
-      for (int c = 0; c < Q; ++c) {
-        T s0 = 0;
-#pragma unroll
-        for (int m = 0; m < Q; ++m) s0 += sJ[m][jc] * B[(c * Q + m) * RP + ic];
-        S[c] = pin(s0);
-        level_fence();
+      for (int b = 0; b < EO::ROWS; ++b) {
+        T ya, yb;
+        eo_row<Q, P1, 1>(tJ, b, f1, ya, yb);
+        B2[b * LB + ob] = ya;
+        if (b < EO::HO) B2[(Q - 1 - b) * LB + ob] = yb;
       }
     }
-    // back along t in registers and scatter: w(i, j, k) += sum_c J^[c][k] S[c]
+  }
+  __syncthreads();
+  // 3: along r, the quadrature points, and back along r
+  double en = 0.0;
+  if (l < QQ) {
+    T y[P1];
 #pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      T s = 0;
+    for (int i = 0; i < P1; ++i) y[i] = B0[rrow + i];
+    const Folded<P1, T> f0 = fold(y);
+    if constexpr (!STIFF) {
+      Unfold<P1, T> z;
+      z.zero();
 #pragma unroll
-      for (int c = 0; c < Q; ++c) s += Jg[c * P1 + k] * S[c];
+      for (int a = 0; a < EO::ROWS; ++a) {
+        const bool pair = a < EO::HO;
+        T xa, xb;
+        eo_row<Q, P1, 1>(tJ, a, f0, xa, xb);
+        const T va = g[0][a] * xa;
+        const T vb = pair ? g[0][Q - 1 - a] * xb : T(0);
+        if (live) en += (double)xa * (double)va + (pair ? (double)xb * (double)vb : 0.0);
+        z.template add<Q, 1>(tJ, a, va, vb);
+      }
+      z.get(y);
+#pragma unroll
+      for (int i = 0; i < P1; ++i) B0[rrow + i] = y[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < P1; ++i) y[i] = B1[rrow + i];
+      const Folded<P1, T> f1 = fold(y);
+#pragma unroll
+      for (int i = 0; i < P1; ++i) y[i] = B2[rrow + i];
+      const Folded<P1, T> f2 = fold(y);
+      T bq[HELM ? Q : 1];
+      if constexpr (HELM) {
+        const T *Be = Bb + ec * NQ + rl;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) bq[a] = Be[a * QQ];
+      }
+      Unfold<P1, T> zp, zr, zt;
+      zp.zero();
+      zr.zero();
+      zt.zero();
+#pragma unroll
+      for (int a = 0; a < EO::ROWS; ++a) {
+        const bool pair = a < EO::HO;
+        const int b = Q - 1 - a;
+        T ra, rb, sa, sb, ta, tb;
+        eo_row<Q, P1, -1>(tD, a, f0, ra, rb);
+        eo_row<Q, P1, 1>(tJ, a, f1, sa, sb);
+        eo_row<Q, P1, 1>(tJ, a, f2, ta, tb);
+        const T vra = g[0][a] * ra + g[1][a] * sa + g[2][a] * ta;
+        const T vsa = g[1][a] * ra + g[3][a] * sa + g[4][a] * ta;
+        const T vta = g[2][a] * ra + g[4][a] * sa + g[5][a] * ta;
+        T vrb = 0, vsb = 0, vtb = 0;
+        if (pair) {
+          vrb = g[0][b] * rb + g[1][b] * sb + g[2][b] * tb;
+          vsb = g[1][b] * rb + g[3][b] * sb + g[4][b] * tb;
+          vtb = g[2][b] * rb + g[4][b] * sb + g[5][b] * tb;
+        }
+        if (live) {
+          en += (double)ra * (double)vra + (double)sa * (double)vsa + (double)ta * (double)vta;
+          if (pair)
+            en += (double)rb * (double)vrb + (double)sb * (double)vsb + (double)tb * (double)vtb;
+        }
+        zp.template add<Q, -1>(tD, a, vra, vrb);
+        zr.template add<Q, 1>(tJ, a, vsa, vsb);
+        zt.template add<Q, 1>(tJ, a, vta, vtb);
+        if constexpr (HELM) {
+          T xa, xb;
+          eo_row<Q, P1, 1>(tJ, a, f0, xa, xb);
+          const T wa = bq[a] * xa;
+          const T wb = pair ? bq[b] * xb : T(0);
+          if (live) en += (double)xa * (double)wa + (pair ? (double)xb * (double)wb : 0.0);
+          zp.template add<Q, 1>(tJ, a, wa, wb);
+        }
+      }
+      zp.get(y);
+#pragma unroll
+      for (int i = 0; i < P1; ++i) B0[rrow + i] = y[i];
+      zr.get(y);
+#pragma unroll
+      for (int i = 0; i < P1; ++i) B1[rrow + i] = y[i];
+      zt.get(y);
+#pragma unroll
+      for (int i = 0; i < P1; ++i) B2[rrow + i] = y[i];
+    }
+  }
+  __syncthreads();
+  // 4: back along s (pencil (i, c) = lane l), into the A tiles in place
+  if (spn) {
+    const int ob = (l / P1) * RS + l % P1;
+    Unfold<P1, T> s1, s2;
+    s1.zero();
+    if constexpr (STIFF) s2.zero();
+#pragma unroll
+    for (int b = 0; b < EO::ROWS; ++b) {
+      const bool pair = b < EO::HO;
+      const int bm = (Q - 1 - b) * LB + ob;
+      s1.template add<Q, 1>(tJ, b, B0[b * LB + ob], pair ? B0[bm] : T(0));
+      if constexpr (STIFF) {
+        s1.template add<Q, -1>(tD, b, B1[b * LB + ob], pair ? B1[bm] : T(0));
+        s2.template add<Q, 1>(tJ, b, B2[b * LB + ob], pair ? B2[bm] : T(0));
+      }
+    }
+    T z[P1];
+    s1.get(z);
+#pragma unroll
+    for (int j = 0; j < P1; ++j) A0[j * LA + l] = z[j];
+    if constexpr (STIFF) {
+      s2.get(z);
+#pragma unroll
+      for (int j = 0; j < P1; ++j) A1[j * LA + l] = z[j];
+    }
+  }
+  __syncthreads();
+  // 5: back along t and scatter
+  if (col) {
+    const T *a0 = A0 + cj * LA + ci;
+    const T *a1 = A1 + cj * LA + ci;
+    Unfold<P1, T> wz;
+    wz.zero();
+#pragma unroll
+    for (int c = 0; c < EO::ROWS; ++c) {
+      const bool pair = c < EO::HO;
+      wz.template add<Q, 1>(tJ, c, a0[c * P1], pair ? a0[(Q - 1 - c) * P1] : T(0));
+      if constexpr (STIFF)
+        wz.template add<Q, -1>(tD, c, a1[c * P1], pair ? a1[(Q - 1 - c) * P1] : T(0));
+    }
+    T wk[P1];
+    wz.get(wk);
+#pragma unroll
+    for (int k = 0; k < P1; ++k)
       if (mb >> k & 1u) {
         if constexpr (LOCAL)  // element-local output, one lane per entry: no assembly
-          w[gk[k]] = accum ? w[gk[k]] + s : s;
+          w[gk[k]] = wk[k];
         else
-          atomic_add(w + gk[k], s);
+          atomic_add(w + gk[k], wk[k]);
       }
-    }
-    double enb[1] = {en};
-    if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + c0, 1);
   }
+  double enb[1] = {en};
+  if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + c0, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,8 +702,10 @@ __global__ __launch_bounds__((QPlane<Q, STIFF>::THREADS), 2) void k_op_interp(
 // dx_l/dr_m are taken there with D~ (exact: x is a polynomial of degree p < q
 // in each variable), and the inverse Jacobian comes from the cofactor matrix:
 // G_mm' = sum_l cof_lm cof_lm' w / det and B~ = det w, w the product of the
-// 1D weights. `bad` receives the smallest element index with det <= 0 (or
-// non-finite) at some point. Dynamic LDS: two regions, A (coordinates, then
+// 1D weights. Gauss-Legendre operators store the point index reversed
+// ([a][b][c], c fastest; the layout their kernel reads coalesced). `bad`
+// receives the smallest element index with det <= 0 (or non-finite) at some
+// point. Dynamic LDS: two regions, A (coordinates, then
 // the j-pass) and B (the i-pass, then the coordinates at the points).
 // basis: J^ (q x p1) | D^ (q x p1) | D~ (q x q) | 1D weights (q).
 // ---------------------------------------------------------------------------
@@ -651,15 +779,16 @@ __global__ __launch_bounds__(256) void k_geometry(int64_t nelem, int p1, int q, 
       if (!(det > 0.0) || !isfinite(det)) atomicMin(bad, (int)e);
       const double wq = rho[a] * rho[bq] * rho[c];
       const double sc = wq / det;
+      const int ns = colloc ? n : (a * q + bq) * q + c;  // stored point index
       int comp = 0;
       for (int m = 0; m < 3; ++m)
         for (int mp = m; mp < 3; ++mp) {
           double g = 0.0;
           for (int l = 0; l < 3; ++l) g += cof[l][m] * cof[l][mp];
-          G[(e * 6 + comp) * nq + n] = g * sc;
+          G[(e * 6 + comp) * nq + ns] = g * sc;
           ++comp;
         }
-      Bt[e * nq + n] = det * wq;
+      Bt[e * nq + ns] = det * wq;
     }
     __syncthreads();  // the regions are rewritten for the next element
   }
@@ -672,12 +801,13 @@ __global__ __launch_bounds__(256) void k_geometry(int64_t nelem, int p1, int q, 
 // phi_3 = J[a][i] J[b][j] D[c][k]; mass: sum B~ J[a][i]^2 J[b][j]^2 J[c][k]^2.
 // Sum-factorised per element (contract a, then b, then c), scatter-added.
 // Runtime sizes; dynamic LDS of q^3 + q^2 p1 + q p1^2 + p1^3 + 2 q p1 values.
+// rev: the quadrature data are stored with the point index reversed.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_diag(int64_t nelem, int p1, int q, int stiff,
                                               const int32_t *__restrict__ idx,
                                               const double *__restrict__ Gm,
                                               const double *__restrict__ basis,
-                                              double *__restrict__ d, int masked) {
+                                              double *__restrict__ d, int masked, int rev) {
   extern __shared__ double dsm[];
   const int q3 = q * q * q, n3 = p1 * p1 * p1;
   double *sg = dsm;                // [c][b][a]      q^3
@@ -699,7 +829,8 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nelem, int p1, int q, int 
     __syncthreads();
     for (int term = 0; term < nterms; ++term) {
       const double *src = stiff ? Gm + (e * 6 + term) * q3 : Gm + e * q3;
-      for (int x = t; x < q3; x += nt) sg[x] = src[x];
+      for (int x = t; x < q3; x += nt)
+        sg[x] = src[rev ? (x % q * q + x / q % q) * q + x / (q * q) : x];
       const int m0 = stiff ? pm[term] : -1, m1 = stiff ? pn[term] : -1;
       const double fac = (stiff && m0 != m1) ? 2.0 : 1.0;
       __syncthreads();

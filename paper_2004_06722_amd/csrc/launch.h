@@ -43,11 +43,14 @@ int64_t vec_blocks(int64_t n);
 int64_t grid_blocks(int64_t n);
 void fill_f64(double *x, int64_t n, double v, hipStream_t s);
 void fill_f32(float *x, int64_t n, float v, hipStream_t s);
-void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,
+// Gk = kappa G per point (and its FP32 copy if Gk32); kappa is in the caller's
+// [E][c][b][a] point order, G stored reversed when qrev = q (else qrev = 0)
+void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32, int qrev,
                     int64_t nelem, int nq, hipStream_t s);
-// Bb = beta_q * Bt (beta_q NULL: the constant beta), and its FP32 copy if Bb32
+// Bb = beta_q * Bt (beta_q NULL: the constant beta), and its FP32 copy if Bb32;
+// point orders as for scale_geometry
 void scale_mass(const double *Bt, const double *beta_q, double beta, double *Bb, float *Bb32,
-                int64_t count, hipStream_t s);
+                int nq, int qrev, int64_t count, hipStream_t s);
 void to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStream_t s);
 

@@ -7,23 +7,15 @@
 namespace bp {
 
 // Elements per work-group of the operator kernel for (p1, q, which); the
-// Gauss-Legendre values mirror QPlane, the GLL ones Plane.
+// Gauss-Legendre values mirror GLPlane, the GLL ones Plane.
 int64_t plane_epb(int p1, int q, int which) {
-  if (q > p1) {  // Gauss-Legendre kernels: q x q planes in up to 256 threads
-    if (which == BP_STIFF && (q == 8 || q == 10)) return q == 8 ? 3 : 1;
-    const int n = q * q;
-    return n >= 256 ? 1 : 256 / n;
-  }
+  if (q > p1) return gl_epb(p1, q, which == BP_MASS ? kGLMass : kGLStiff);
   const int n = p1 * p1;
   return n >= 64 ? 1 : 64 / n;
 }
 
 int64_t apply_rows(const bp_op_s *op, int which) {
-  if (which == BP_HELM) {
-    // GL: the stiffness launch, then the beta-mass launch writes its rows
-    const int64_t st = apply_rows(op, BP_STIFF);
-    return op->colloc || !op->Bb ? st : st + apply_rows(op, BP_MASS);
-  }
+  // BP_HELM runs in one launch of the stiffness layout (GL and GLL)
   const int64_t epb = plane_epb(op->p1, op->q, which);
   return (op->nelem + epb - 1) / epb;
 }
@@ -69,25 +61,24 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
   return BP_OK;
 }
 
-template <int P1, int Q, typename T, bool STIFF, bool LOCAL>
-int interp(const bp_op_s *op, const T *Gm, const T *basis, const T *u, T *w, int masked,
-           double *part, const int *done, hipStream_t s, int accum = 0) {
-  using PL = QPlane<Q, STIFF>;
+template <int P1, int Q, typename T, int MODE, bool LOCAL>
+int gauss(const bp_op_s *op, const T *Gm, const T *Bb, const T *basis, const T *u, T *w,
+          int masked, double *part, const int *done, hipStream_t s) {
+  using PL = GLPlane<P1, Q, MODE>;
   static_assert(PL::EPB * Q * Q <= 256, "plane layout");
-  const int64_t grid = apply_rows(op, STIFF ? BP_STIFF : BP_MASS);
-  if (grid != (op->nelem + PL::EPB - 1) / PL::EPB) return set_error(BP_ERR_ARG, "plane layout");
+  const int64_t grid = (op->nelem + PL::EPB - 1) / PL::EPB;
+  if (grid != apply_rows(op, MODE == kGLMass ? BP_MASS : BP_STIFF))
+    return set_error(BP_ERR_ARG, "plane layout");
   const int64_t cs = vec_stride<LOCAL>(op);
   for (int c = 0; c < op->ncomp; ++c)
-    hipLaunchKernelGGL((k_op_interp<P1, Q, T, STIFF, LOCAL>), dim3(grid), dim3(PL::THREADS), 0,
-                       s, op->nelem, op->idx, Gm, basis, u + c * cs, w + c * cs, op->ncomp, c,
-                       masked, accum, part, done);
+    hipLaunchKernelGGL((k_op_gl<P1, Q, T, MODE, LOCAL>), dim3(grid), dim3(PL::THREADS), 0, s,
+                       op->nelem, op->idx, Gm, Bb, basis, u + c * cs, w + c * cs, op->ncomp, c,
+                       masked, part, done);
   return BP_OK;
 }
 
-// which = BP_HELM: H = A + B_beta (eq. (hm2)). With GLL the beta term is fused
-// into the stiffness kernel; with GL points the mass kernel runs after the
-// stiffness kernel with beta B~ in place of B~, adding into the same w, and
-// writes its energy partials after the stiffness ones.
+// which = BP_HELM: H = A + B_beta (eq. (hm2)), the beta term fused into the
+// stiffness kernel (GLL: diagonal mass; GL: one more J^ chain at the points).
 template <typename T, bool LOCAL>
 int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *Bb,
              const T *basis, const T *u, T *w, int masked, double *part, const int *done,
@@ -107,16 +98,15 @@ int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *Bb,
     }
 #undef BP_CASE
   } else if (op->q == op->p1 + 1) {
-    double *part2 = part ? part + apply_rows(op, BP_STIFF) * op->ncomp : nullptr;
-#define BP_CASE(P)                                                                             \
-  case P: {                                                                                    \
-    if (!stiff) return interp<P, P + 1, T, false, LOCAL>(op, Bt, basis, u, w, masked, part,   \
-                                                         done, s);                             \
-    int rc = interp<P, P + 1, T, true, LOCAL>(op, G, basis, u, w, masked, part, done, s);      \
-    if (rc == BP_OK && helm)                                                                   \
-      rc = interp<P, P + 1, T, false, LOCAL>(op, Bb, basis, u, w, masked, part2, done, s, 1);  \
-    return rc;                                                                                 \
-  }
+#define BP_CASE(P)                                                                         \
+  case P:                                                                                  \
+    if (!stiff)                                                                            \
+      return gauss<P, P + 1, T, kGLMass, LOCAL>(op, Bt, Bb, basis, u, w, masked, part,     \
+                                                done, s);                                  \
+    return helm ? gauss<P, P + 1, T, kGLHelm, LOCAL>(op, G, Bb, basis, u, w, masked, part, \
+                                                     done, s)                              \
+                : gauss<P, P + 1, T, kGLStiff, LOCAL>(op, G, Bb, basis, u, w, masked,      \
+                                                      part, done, s);
     switch (op->p1) {
       BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
     }
@@ -187,7 +177,7 @@ int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_
     const bool stiff = part == 0 && which != BP_MASS;
     const double *Gm = stiff ? (op->kappa_set ? op->Gk : op->G) : (part == 1 ? op->Bb : op->Bt);
     hipLaunchKernelGGL(k_diag, dim3(grid), dim3(256), lds, s, op->nelem, p1, q, stiff ? 1 : 0,
-                       op->idx, Gm, op->basis_d, d, masked ? 1 : 0);
+                       op->idx, Gm, op->basis_d, d, masked ? 1 : 0, op->colloc ? 0 : 1);
     BP_HIP(hipGetLastError());
   }
   return BP_OK;

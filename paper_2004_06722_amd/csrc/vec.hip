@@ -331,17 +331,25 @@ __global__ __launch_bounds__(kVecThreads) void k_invert(const double *__restrict
 }
 
 // Gk[e][m][q] = kappa[e][q] * G[e][m][q]
+// Index in the caller's [c][b][a] point order of stored point qp (qrev = q:
+// stored reversed, [a][b][c]; 0: same order).
+__device__ __forceinline__ int64_t natural_point(int64_t qp, int qrev) {
+  if (!qrev) return qp;
+  const int64_t a = qp / ((int64_t)qrev * qrev), b = qp / qrev % qrev, c = qp % qrev;
+  return (c * qrev + b) * qrev + a;
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_scale_geometry(const double *__restrict__ G,
                                                                 const double *__restrict__ kap,
                                                                 double *__restrict__ Gk,
                                                                 float *__restrict__ Gk32,
-                                                                int64_t nelem, int nq) {
+                                                                int64_t nelem, int nq, int qrev) {
   const int64_t total = nelem * 6 * nq;
   for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * kVecThreads) {
     const int64_t e = i / (6 * (int64_t)nq);
     const int64_t qp = i % nq;
-    const double v = kap[e * nq + qp] * G[i];
+    const double v = kap[e * nq + natural_point(qp, qrev)] * G[i];
     Gk[i] = v;
     if (Gk32) Gk32[i] = (float)v;
   }
@@ -501,10 +509,11 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_mass(const double *__rest
                                                             const double *__restrict__ beta_q,
                                                             double beta, double *__restrict__ Bb,
                                                             float *__restrict__ Bb32,
-                                                            int64_t count) {
+                                                            int64_t count, int nq, int qrev) {
   for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * kVecThreads) {
-    const double v = (beta_q ? beta_q[i] : beta) * Bt[i];
+    const double bq = beta_q ? beta_q[i / nq * nq + natural_point(i % nq, qrev)] : beta;
+    const double v = bq * Bt[i];
     Bb[i] = v;
     if (Bb32) Bb32[i] = (float)v;
   }
@@ -552,10 +561,10 @@ void to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
 void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_invert, dim3(grid_blocks(n)), dim3(kVecThreads), 0, s, d, dinv, dinv32, n);
 }
-void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32,
+void scale_geometry(const double *G, const double *kappa, double *Gk, float *Gk32, int qrev,
                     int64_t nelem, int nq, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_geometry, dim3(grid_blocks(nelem * 6 * nq)), dim3(kVecThreads), 0, s,
-                     G, kappa, Gk, Gk32, nelem, nq);
+                     G, kappa, Gk, Gk32, nelem, nq, qrev);
 }
 
 // after a residual replacement that ended an iteration before its direction
@@ -621,9 +630,9 @@ static void launch_fin(FinKind k, int nc, const double *src, int64_t rows, DevSc
 }
 
 void scale_mass(const double *Bt, const double *beta_q, double beta, double *Bb, float *Bb32,
-                int64_t count, hipStream_t s) {
+                int nq, int qrev, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_mass, dim3(grid_blocks(count)), dim3(kVecThreads), 0, s, Bt, beta_q,
-                     beta, Bb, Bb32, count);
+                     beta, Bb, Bb32, count, nq, qrev);
 }
 
 template <typename T>
