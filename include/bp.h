@@ -75,8 +75,8 @@ int bp_rule(int n, int quad, double *x, double *w);
  * all precomputed as section 3 requires.
  *   p in [1, 15]; q in [2, 16]; quad = BP_QUAD_GL or BP_QUAD_GLL (GLL needs
  *   q = p + 1, collocated); ncomp in [1, 8] components per node.
- *   The compiled kernels cover p <= 8 with (quad, q) = (GLL, p+1) or
- *   (GL, p+2); other combinations return BP_ERR_ARG.
+ *   The compiled kernels cover (quad, q) = (GLL, p+1) for p <= 15 and
+ *   (GL, p+2) for p <= 8; other combinations return BP_ERR_ARG.
  *   nelem >= 1; nglobal in [1, 2^31 - 1].
  *   elem_dofs: host int64 [nelem][p1^3], global node id of each local node,
  *     0 <= id < nglobal. The map is treated as arbitrary (no tensor layout).
@@ -219,6 +219,7 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
  * coefficient (section 4 eq. (ip1) with mu = kappa; section 5 eq. (bk5x)),
  * summed over the ncomp components. lam, u: device double [ncomp][nglobal]
  * (masked on Dirichlet nodes); g: device double [nelem][q^3], overwritten.
+ * Collocated GLL operators with p <= 8; others return BP_ERR_ARG.
  */
 int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
                   void *stream);

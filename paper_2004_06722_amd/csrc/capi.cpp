@@ -446,7 +446,7 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   if (!kernels_cover(p, q, quad))
     return set_error(BP_ERR_ARG, "bp_setup: no compiled kernels for p=" + std::to_string(p) +
                                      ", q=" + std::to_string(q) +
-                                     " (compiled: p <= 8 with GLL q=p+1 or GL q=p+2)");
+                                     " (compiled: GLL q=p+1 with p <= 15, GL q=p+2 with p <= 8)");
   hipStream_t s = (hipStream_t)stream;
   const int p1 = p + 1;
   const int64_t n3 = (int64_t)p1 * p1 * p1, nq = (int64_t)q * q * q;

@@ -705,9 +705,10 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
 // 1D weights. Gauss-Legendre operators store the point index reversed
 // ([a][b][c], c fastest; the layout their kernel reads coalesced). `bad`
 // receives the smallest element index with det <= 0 (or non-finite) at some
-// point. Dynamic LDS: two regions, A (coordinates, then
-// the j-pass) and B (the i-pass, then the coordinates at the points).
-// basis: J^ (q x p1) | D^ (q x p1) | D~ (q x q) | 1D weights (q).
+// point. Dynamic LDS (interpolating rules only): two regions, A (coordinates,
+// then the j-pass) and B (the i-pass, then the coordinates at the points);
+// with collocated GLL points the derivatives are taken straight from the
+// coordinate array. basis: J^ (q x p1) | D^ (q x p1) | D~ (q x q) | 1D weights (q).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_geometry(int64_t nelem, int p1, int q, int colloc,
                                                   const double *__restrict__ X,
@@ -721,10 +722,10 @@ __global__ __launch_bounds__(256) void k_geometry(int64_t nelem, int p1, int q, 
   const double *J = basis, *Dq = basis + 2 * q * p1, *rho = basis + 2 * q * p1 + q * q;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
-    for (int x = t; x < 3 * n3; x += nt) A[x] = X[e * 3 * n3 + x];
-    __syncthreads();
-    const double *Xq = A;
+    const double *Xq = X + e * 3 * n3;  // collocated: the nodes are the points
     if (!colloc) {
+      for (int x = t; x < 3 * n3; x += nt) A[x] = Xq[x];
+      __syncthreads();
       // along i: B[k][j][a][l] = sum_i J^[a][i] X[k][j][i][l]
       for (int x = t; x < 3 * p1 * p1 * q; x += nt) {
         const int l = x % 3, a = (x / 3) % q, kj = x / (3 * q);

@@ -95,6 +95,7 @@ int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *Bb,
                                                    done, s);
     switch (op->p1) {
       BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
+      BP_CASE(10) BP_CASE(11) BP_CASE(12) BP_CASE(13) BP_CASE(14) BP_CASE(15) BP_CASE(16)
     }
 #undef BP_CASE
   } else if (op->q == op->p1 + 1) {
@@ -126,9 +127,9 @@ void grad_colloc(const bp_op_s *op, const double *lam, const double *u, double *
 }  // namespace
 
 bool kernels_cover(int p, int q, int quad) {
-  if (p < 1 || p > 8) return false;
-  if (quad == BP_QUAD_GLL) return q == p + 1;
-  return q == p + 2;
+  if (p < 1) return false;
+  if (quad == BP_QUAD_GLL) return p <= 15 && q == p + 1;
+  return p <= 8 && q == p + 2;
 }
 
 template <bool LOCAL>
@@ -171,6 +172,9 @@ int launch_diag(const bp_op_s *op, int which, double *d, bool masked, hipStream_
                      ((size_t)q * q * q + (size_t)q * q * p1 + (size_t)q * p1 * p1 +
                       (size_t)p1 * p1 * p1 + 2 * (size_t)q * p1);
   const int64_t grid = op->nelem < 65536 ? op->nelem : 65536;
+  if (lds > 65536)  // high orders: more than the default dynamic LDS per work-group
+    BP_HIP(hipFuncSetAttribute((const void *)k_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
   // BP_HELM: diag(A) + diag(B_beta), both added into d
   const bool helm = which == BP_HELM && op->Bb != nullptr;
   for (int part = 0; part < (helm ? 2 : 1); ++part) {
@@ -188,8 +192,9 @@ int launch_geometry(const bp_op_s *op, const double *X, double *G, double *Bt, i
   const int p1 = op->p1, q = op->q;
   const size_t n3 = (size_t)p1 * p1 * p1, nq = (size_t)q * q * q;
   const size_t ra = 3 * std::max(n3, (size_t)p1 * q * q), rb = 3 * std::max((size_t)p1 * p1 * q, nq);
+  const size_t lds = op->colloc ? 0 : (ra + rb) * sizeof(double);
   const int64_t grid = op->nelem < 65536 ? op->nelem : 65536;
-  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(256), (ra + rb) * sizeof(double), s, op->nelem,
+  hipLaunchKernelGGL(k_geometry, dim3(grid), dim3(256), lds, s, op->nelem,
                      p1, q, op->colloc ? 1 : 0, X, op->basis_d, G, Bt, bad);
   BP_HIP(hipGetLastError());
   return BP_OK;
@@ -207,7 +212,7 @@ int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, dou
     case 7: grad_colloc<7>(op, lam, u, g, s); break;
     case 8: grad_colloc<8>(op, lam, u, g, s); break;
     case 9: grad_colloc<9>(op, lam, u, g, s); break;
-    default: return set_error(BP_ERR_ARG, "bp_grad_kappa: order not compiled");
+    default: return set_error(BP_ERR_ARG, "bp_grad_kappa: compiled for p <= 8");
   }
   BP_HIP(hipGetLastError());
   return BP_OK;

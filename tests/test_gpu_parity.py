@@ -348,7 +348,7 @@ def test_errors_are_reported():
     with pytest.raises(BpError, match="element 1"):
         B.Operator(3, 4, B.GLL, m.elem_dofs, xyz, m.nglobal)
     with pytest.raises(BpError, match="BP_ERR_ARG"):
-        B.Operator(9, 10, B.GLL, np.zeros((1, 1000), np.int64), np.zeros((1, 1000, 3)), 1000)
+        B.Operator(9, 11, B.GL, np.zeros((1, 1000), np.int64), np.zeros((1, 1000, 3)), 1000)
     # the device set-up reports the smallest bad element, also on GL points
     m4 = synth.brick_mesh(4, 2, 1, 3, xi, seed=None)
     xyz = m4.node_xyz.copy()

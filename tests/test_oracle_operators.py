@@ -231,3 +231,17 @@ def test_helmholtz_with_zero_beta_is_stiffness_and_is_spd_without_dirichlet():
     H = assemble(disc_b, HELM, masked=False).toarray()
     assert np.allclose(H, H.T, atol=1e-13 * abs(H).max())
     assert np.linalg.eigvalsh(H).min() > 0
+
+
+@pytest.mark.parametrize("p", [11, 15])
+def test_high_order_gll_pins(p):
+    # the oracle at the top of the order range: volume, constants in the null
+    # space and the coordinate energy identity (trilinear geometry, exact with
+    # GLL from p = 2 on)
+    disc, mesh = make_disc(5, p, 2, 1, 1, seed=3, dirichlet=False)
+    one = np.ones(disc.nglobal)
+    assert abs(one @ disc.apply(MASS, one, masked=False) - 1.0) < 1e-13
+    w = disc.apply(STIFF, one, masked=False)
+    assert np.abs(w).max() < 1e-12 * np.abs(disc.diag(STIFF, masked=False)).max()
+    X = mesh.global_coords()
+    assert np.allclose(X.T @ disc.apply(STIFF, X, masked=False), np.eye(3), atol=1e-11)

@@ -54,7 +54,7 @@ def test_gll_exact_to_degree_2q_minus_3(p1):
 
 
 @pytest.mark.parametrize("p,q,quad", [(p, p + 2, "gl") for p in range(1, 10)]
-                         + [(p, p + 1, "gll") for p in range(1, 10)])
+                         + [(p, p + 1, "gll") for p in range(1, 16)])
 def test_interpolation_and_derivative_exact_on_polynomials(p, q, quad):
     r = Rule(p, q, quad)
     for k in range(p + 1):
