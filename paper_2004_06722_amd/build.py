@@ -60,7 +60,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
         objs = list(ex.map(lambda s: compile_one(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp,
-           "-lpthread"]
+           f"-Wl,--version-script={os.path.join(CSRC, 'exports.map')}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

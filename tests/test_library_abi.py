@@ -42,6 +42,9 @@ def test_library_exports_every_declared_symbol(lib):
     for n in declared_functions():
         assert n in exported, n
         assert hasattr(lib, n)
+    # and nothing else: the C++ internals stay local
+    functions = set(re.findall(r"\s[TW]\s(\S+)", out))
+    assert functions == set(declared_functions()), sorted(functions - set(declared_functions()))[:5]
     # the binding declares exactly the header's functions
     assert sorted(_lib.SIGNATURES) == declared_functions()
 
