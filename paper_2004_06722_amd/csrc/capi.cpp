@@ -199,7 +199,10 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   BP_HIP(hipEventRecord(op->ev0, s));
   const int poll = 8;
   int it = 0, timed = 0;
-  const int *done = &op->sc->done;
+  // a fixed number of iterations has no stopping test to honour: the kernels
+  // then skip the done flag (nothing waits on loading it)
+  const bool check = !fixed;
+  const int *done = check ? &op->sc->done : nullptr;
   if (op->time_apply && op->apply_ev.empty()) {
     op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
     for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
@@ -212,10 +215,10 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
       rc = launch_apply(op, which, f32, p, w, masked, op->part, done, s);
       if (rc) return rc;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
-      cg_fin_alpha(nc, op->part, nb_apply, op->sc, s);
-      cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s);
-      cg_fin_beta(nc, nb_vec, op->part, op->sc, s);
-      cg_update_xp<T>(nc, n, x, p, r, dinv, op->sc, s);
+      cg_fin_alpha(nc, op->part, nb_apply, op->sc, s, check);
+      cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s, check);
+      cg_fin_beta(nc, nb_vec, op->part, op->sc, s, check);
+      cg_update_xp<T>(nc, n, x, p, r, dinv, op->sc, s, check);
     }
     BP_HIP(hipGetLastError());
     it += chunk;
@@ -276,7 +279,10 @@ int pcg_run_sr(bp_op op, int which, const double *b, double *x, const double *di
   BP_HIP(hipEventRecord(op->ev0, s));
   const int poll = 8;
   int it = 0, timed = 0;
-  const int *done = &op->sc->done;
+  // a fixed number of iterations has no stopping test to honour: the kernels
+  // then skip the done flag (nothing waits on loading it)
+  const bool check = !fixed;
+  const int *done = check ? &op->sc->done : nullptr;
   if (op->time_apply && op->apply_ev.empty()) {
     op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
     for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));

@@ -58,14 +58,18 @@ void invert_diag(const double *d, double *dinv, float *dinv32, int64_t n, hipStr
 template <typename T>
 void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, double *part,
              DevScalars *sc, hipStream_t s);
-void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s);
+// check = false (a fixed number of iterations): the kernels do not stop on
+// the done flag, so their loads need not wait for it
+void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s,
+                  bool check = true);
 template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
-                 hipStream_t s);
-void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s);
+                 hipStream_t s, bool check = true);
+void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
+                 bool check = true);
 template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
-                  hipStream_t s);
+                  hipStream_t s, bool check = true);
 
 // single-reduction PCG: init (r, u = dinv r, p = s = w = 0; partials r.u, r.r,
 // b.b), the fused vector update (partials r.u, r.r), and the finisher that

@@ -183,9 +183,9 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restri
 
 template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restrict__ part,
-                                                           int64_t nb, DevScalars *sc) {
+                                                           int64_t nb, DevScalars *sc, int check) {
   constexpr int nc = NC;
-  if (sc->done) {
+  if (check && sc->done) {
     if (threadIdx.x == 0) sc->halted = 1;
     return;
   }
@@ -204,11 +204,13 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
 // r -= alpha w; w = 0; partials r.z (z = dinv r) and r.r. The matching
 // x += alpha p is deferred to k_cg_update_xp, which reads p anyway: five
 // vector words here and six there instead of eight and four.
+// check = 0 (a fixed number of iterations): no early exit on the done flag,
+// so the loads do not wait for it (likewise in the other iteration kernels).
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
     int64_t n, T *__restrict__ r, T *__restrict__ w, const T *__restrict__ dinv,
-    double *__restrict__ part, const DevScalars *__restrict__ sc) {
-  if (sc->done) return;
+    double *__restrict__ part, const DevScalars *__restrict__ sc, int check) {
+  if (check && sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   double rz = 0.0, rr = 0.0;
@@ -228,9 +230,9 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
 
 template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restrict__ part,
-                                                          int64_t nb, DevScalars *sc) {
+                                                          int64_t nb, DevScalars *sc, int check) {
   constexpr int nc = NC;
-  if (sc->done) return;
+  if (check && sc->done) return;
   __shared__ double res[2 * NC];
   reduce_columns<2 * NC>(part, nb, res);
   if (threadIdx.x == 0) {
@@ -256,8 +258,9 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xp(int64_t n, T *__re
                                                               T *__restrict__ p,
                                                               const T *__restrict__ r,
                                                               const T *__restrict__ dinv,
-                                                              const DevScalars *__restrict__ sc) {
-  if (sc->halted) return;
+                                                              const DevScalars *__restrict__ sc,
+                                                              int check) {
+  if (check && sc->halted) return;
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   if (v < n) {
     const int comp = blockIdx.y;
@@ -595,16 +598,18 @@ enum class FinKind { Init, Alpha, Beta, Norms, Restart };
 // the single-work-group finisher for nc components (compile-time widths)
 template <int NC>
 static void launch_fin_nc(FinKind k, const double *src, int64_t rows, DevScalars *sc,
-                          hipStream_t s) {
+                          hipStream_t s, int check) {
   switch (k) {
     case FinKind::Init:
       hipLaunchKernelGGL(k_fin_init<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
       break;
     case FinKind::Alpha:
-      hipLaunchKernelGGL(k_fin_alpha<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      hipLaunchKernelGGL(k_fin_alpha<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc,
+                         check);
       break;
     case FinKind::Beta:
-      hipLaunchKernelGGL(k_fin_beta<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      hipLaunchKernelGGL(k_fin_beta<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc,
+                         check);
       break;
     case FinKind::Norms:
       hipLaunchKernelGGL(k_fin_norms<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
@@ -616,16 +621,16 @@ static void launch_fin_nc(FinKind k, const double *src, int64_t rows, DevScalars
 }
 
 static void launch_fin(FinKind k, int nc, const double *src, int64_t rows, DevScalars *sc,
-                       hipStream_t s) {
+                       hipStream_t s, int check = 1) {
   switch (nc) {
-    case 1: launch_fin_nc<1>(k, src, rows, sc, s); break;
-    case 2: launch_fin_nc<2>(k, src, rows, sc, s); break;
-    case 3: launch_fin_nc<3>(k, src, rows, sc, s); break;
-    case 4: launch_fin_nc<4>(k, src, rows, sc, s); break;
-    case 5: launch_fin_nc<5>(k, src, rows, sc, s); break;
-    case 6: launch_fin_nc<6>(k, src, rows, sc, s); break;
-    case 7: launch_fin_nc<7>(k, src, rows, sc, s); break;
-    default: launch_fin_nc<kMaxComp>(k, src, rows, sc, s); break;
+    case 1: launch_fin_nc<1>(k, src, rows, sc, s, check); break;
+    case 2: launch_fin_nc<2>(k, src, rows, sc, s, check); break;
+    case 3: launch_fin_nc<3>(k, src, rows, sc, s, check); break;
+    case 4: launch_fin_nc<4>(k, src, rows, sc, s, check); break;
+    case 5: launch_fin_nc<5>(k, src, rows, sc, s, check); break;
+    case 6: launch_fin_nc<6>(k, src, rows, sc, s, check); break;
+    case 7: launch_fin_nc<7>(k, src, rows, sc, s, check); break;
+    default: launch_fin_nc<kMaxComp>(k, src, rows, sc, s, check); break;
   }
 }
 
@@ -646,31 +651,33 @@ void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, dou
   launch_fin(FinKind::Init, nc, src, rows, sc, s);
 }
 
-void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s) {
+void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s,
+                  bool check) {
   int64_t rows = 0;
   const double *src = reduce_stage1(part, nb, nc, const_cast<double *>(part) + nb * nc, &rows, s);
-  launch_fin(FinKind::Alpha, nc, src, rows, sc, s);
+  launch_fin(FinKind::Alpha, nc, src, rows, sc, s, check ? 1 : 0);
 }
 
 template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
-                 hipStream_t s) {
+                 hipStream_t s, bool check) {
   hipLaunchKernelGGL((k_cg_update_r<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, r,
-                     w, dinv, part, sc);
+                     w, dinv, part, sc, check ? 1 : 0);
 }
 
-void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s) {
+void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
+                 bool check) {
   int64_t rows = 0;
   const double *src =
       reduce_stage1(part, nb, 2 * nc, const_cast<double *>(part) + nb * 2 * nc, &rows, s);
-  launch_fin(FinKind::Beta, nc, src, rows, sc, s);
+  launch_fin(FinKind::Beta, nc, src, rows, sc, s, check ? 1 : 0);
 }
 
 template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
-                  hipStream_t s) {
+                  hipStream_t s, bool check) {
   hipLaunchKernelGGL((k_cg_update_xp<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x,
-                     p, r, dinv, sc);
+                     p, r, dinv, sc, check ? 1 : 0);
 }
 
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
@@ -757,12 +764,12 @@ template void cg_init<double>(int, int64_t, const double *, double *, double *, 
 template void cg_init<float>(int, int64_t, const float *, float *, float *, float *,
                              const float *, double *, DevScalars *, hipStream_t);
 template void cg_update_r<double>(int, int64_t, double *, double *, const double *, double *,
-                                  DevScalars *, hipStream_t);
+                                  DevScalars *, hipStream_t, bool);
 template void cg_update_r<float>(int, int64_t, float *, float *, const float *, double *,
-                                 DevScalars *, hipStream_t);
+                                 DevScalars *, hipStream_t, bool);
 template void cg_update_xp<double>(int, int64_t, double *, double *, const double *,
-                                   const double *, DevScalars *, hipStream_t);
+                                   const double *, DevScalars *, hipStream_t, bool);
 template void cg_update_xp<float>(int, int64_t, float *, float *, const float *, const float *,
-                                  DevScalars *, hipStream_t);
+                                  DevScalars *, hipStream_t, bool);
 
 }  // namespace bp
