@@ -170,7 +170,9 @@ int download_scalars(bp_op op, hipStream_t s) {
 }
 
 // Jacobi-PCG on precision T. x0_zero: x is zero on entry (skips A x0).
-// resume: continue from the device scalars and the r, p, w (w zero) that a
+// The buffer `r` holds the preconditioned residual z = dinv r during the
+// iteration (ten vector words per DOF and iteration; see k_cg_init).
+// resume: continue from the device scalars and the z, p, w (w zero) that a
 // previous call or cg_restart left, without the set-up (b, rtol unused).
 template <typename T>
 int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r, T *p, T *w,
@@ -218,7 +220,7 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
       cg_fin_alpha(nc, op->part, nb_apply, op->sc, s, check);
       cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s, check);
       cg_fin_beta(nc, nb_vec, op->part, op->sc, s, check);
-      cg_update_xp<T>(nc, n, x, p, r, dinv, op->sc, s, check);
+      cg_update_xp<T>(nc, n, x, p, r, op->sc, s, check);
     }
     BP_HIP(hipGetLastError());
     it += chunk;

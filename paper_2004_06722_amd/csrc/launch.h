@@ -68,8 +68,8 @@ void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, Dev
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
                  bool check = true);
 template <typename T>
-void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *r, const T *dinv, DevScalars *sc,
-                  hipStream_t s, bool check = true);
+void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
+                  bool check = true);
 
 // single-reduction PCG: init (r, u = dinv r, p = s = w = 0; partials r.u, r.r,
 // b.b), the fused vector update (partials r.u, r.r), and the finisher that
@@ -84,11 +84,12 @@ void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba
             DevScalars *sc, hipStream_t s);
 
 // residual replacement after an iteration that stopped before its direction
-// update: r.z and r.r of the new residual r, then the pending p = z + beta p
-// with beta = (r.z)_new / (r.z)_old (the search direction is kept); r.r
-// becomes the reference norm; clears done/halted
+// update: r holds the new residual and becomes z = dinv r (the form the
+// iteration keeps); r.z and r.r of it, then the pending p = z + beta p with
+// beta = (r.z)_new / (r.z)_old (the search direction is kept); r.r becomes
+// the reference norm; clears done/halted
 template <typename T>
-void cg_restart(int nc, int64_t n, const T *r, T *p, const T *dinv, double *part,
+void cg_restart(int nc, int64_t n, T *r, T *p, const T *dinv, double *part,
                 DevScalars *sc, hipStream_t s);
 
 // defect correction helpers (FP64 outer loop)

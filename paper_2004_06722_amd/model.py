@@ -5,10 +5,10 @@ geometric factors (section 5 after eq. (gij): 6 q^3 words per element for the
 stiffness, q^3 for B~ of eq. (mass)), the int32 gather map (p1^3 per element;
 the global tensor layout may not be exploited, section 3), and the vectors.
 Vector words per DOF and iteration: the operator reads p and writes w (2),
-the CG updates move 11: the residual update reads r, w, dinv and writes r
-and the zeroed w for the next scatter (5), the solution and direction
-update reads x, p, r, dinv and writes x, p (6). 13 in all. DOFs are n = p^3 E
-(section 2) per component.
+the CG updates move 10 with the preconditioned residual z = D^-1 r kept in
+place of r: the residual update reads z, w, dinv and writes z and the zeroed
+w for the next scatter (5), the solution and direction update reads x, p, z
+and writes x, p (5). 12 in all. DOFs are n = p^3 E (section 2) per component.
 
 Flops follow section 5: eq. (work2)/(work3) for the sum-factorised
 stiffness, 4 p1^4 (g^3 + g^2 + g) for the mass, with J^ = I for collocated
@@ -17,7 +17,7 @@ GLL (the derivative contractions alone: 12 p1^4 + 15 p1^3).
 from __future__ import annotations
 
 VECTOR_WORDS_OPERATOR = 2
-VECTOR_WORDS_CG = 11
+VECTOR_WORDS_CG = 10
 
 
 def quadrature(bp: int, p: int) -> int:
