@@ -16,6 +16,28 @@ namespace {
 
 constexpr int kFinThreads = 1024;
 
+// Streaming access for the CG vectors when NT: each is touched once per
+// kernel, and vectors larger than the last-level cache gain from the
+// nontemporal hint (measured: 6.37 against 5.79 TB/s for the 3-read, 2-write
+// direction update at 9e7 nodes); smaller ones lose by it (they are still
+// cached when the next kernel reads them), so the launchers pick NT by size.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_v(const T *p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_v(T *p, T v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+// vectors of at least this many bytes per component stream with NT
+constexpr int64_t kStreamBytes = int64_t(64) << 20;
+
 // Fixed-order sum of W columns over nb rows into res[col] (shared): thread t
 // adds rows t, t + 1024, ... of every column in order (D loads in flight per
 // column), each wave folds its 64 lanes with a fixed shuffle tree, and the
@@ -210,7 +232,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
 // reads p anyway: five vector words here and five there.
 // check = 0 (a fixed number of iterations): no early exit on the done flag,
 // so the loads do not wait for it (likewise in the other iteration kernels).
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
     int64_t n, T *__restrict__ z, T *__restrict__ w, const T *__restrict__ dinv,
     double *__restrict__ part, const DevScalars *__restrict__ sc, int check) {
@@ -221,10 +243,10 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
   if (v < n) {
     const int64_t f = comp * n + v;
     const T al = (T)sc->alpha[comp];
-    const T di = dinv[v];
-    const T zv = z[f] - (al * di) * w[f];
-    z[f] = zv;
-    w[f] = T(0);
+    const T di = ld_v<NT>(dinv + v);
+    const T zv = ld_v<NT>(z + f) - (al * di) * ld_v<NT>(w + f);
+    st_v<NT>(z + f, zv);
+    st_v<NT>(w + f, T(0));
     const T rv = di != T(0) ? zv / di : T(0);
     rz = (double)rv * (double)zv;
     rr = (double)rv * (double)rv;
@@ -258,7 +280,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restri
 // the iteration just converged. `halted` (set by the next k_fin_alpha once
 // done is seen) stops the x update in the launches queued after the last
 // iteration.
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update_xp(int64_t n, T *__restrict__ x,
                                                               T *__restrict__ p,
                                                               const T *__restrict__ z,
@@ -269,9 +291,9 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xp(int64_t n, T *__re
   if (v < n) {
     const int comp = blockIdx.y;
     const int64_t f = comp * n + v;
-    const T pv = p[f];
-    x[f] += (T)sc->alpha[comp] * pv;
-    if (!sc->done) p[f] = z[f] + (T)sc->beta[comp] * pv;
+    const T pv = ld_v<NT>(p + f);
+    st_v<NT>(x + f, ld_v<NT>(x + f) + (T)sc->alpha[comp] * pv);
+    if (!sc->done) st_v<NT>(p + f, ld_v<NT>(z + f) + (T)sc->beta[comp] * pv);
   }
 }
 
@@ -666,8 +688,12 @@ void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStr
 template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
                  hipStream_t s, bool check) {
-  hipLaunchKernelGGL((k_cg_update_r<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, r,
-                     w, dinv, part, sc, check ? 1 : 0);
+  if (n * (int64_t)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_cg_update_r<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
+                       n, r, w, dinv, part, sc, check ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_cg_update_r<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
+                       n, r, w, dinv, part, sc, check ? 1 : 0);
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
@@ -681,8 +707,12 @@ void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStre
 template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
                   bool check) {
-  hipLaunchKernelGGL((k_cg_update_xp<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x,
-                     p, z, sc, check ? 1 : 0);
+  if (n * (int64_t)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_cg_update_xp<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0,
+                       s, n, x, p, z, sc, check ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_cg_update_xp<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0,
+                       s, n, x, p, z, sc, check ? 1 : 0);
 }
 
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
