@@ -183,7 +183,7 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0, helm_beta=None):
         op.pcg_solve(b, which=which, maxit=warmup, fixed_iters=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op.pcg_solve(b, which=which, maxit=steps, fixed_iters=True)
+    _, st_t = op.pcg_solve(b, which=which, maxit=steps, fixed_iters=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # operator average from a second run with per-launch events (the events
@@ -203,7 +203,7 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0, helm_beta=None):
             "apply_avg_ms": apply_ms, "apply_alg_GBs": ab / (apply_ms * 1e-3) / 1e9,
             "apply_frac_hbm": ab / (apply_ms * 1e-3) / 1e9 / model.HBM_PEAK_GBS,
             "iter_alg_frac_hbm": model.iteration_bytes(bp, N, E, ncomp) * steps
-                                 / (st["ms"] * 1e-3) / 1e9 / model.HBM_PEAK_GBS}
+                                 / (st_t["ms"] * 1e-3) / 1e9 / model.HBM_PEAK_GBS}
 
 
 def workload_vector(args):
