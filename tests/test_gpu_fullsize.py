@@ -82,6 +82,27 @@ def test_bp1_bp3_sampled(bp, N, k):
     op.close()
 
 
+def test_bp5_n7_e64cube_fixed_iterations_true_residual():
+    # the benchmark's path (fixed iterations, streamed vectors, z = dinv r kept
+    # in place of r): after k iterations the recursive residual that the
+    # solver reports equals the true residual b - A x_k, and the iterates
+    # reduce the A-norm error monotonically (x_k minimises it over growing
+    # Krylov spaces: the energy E(x) = x.Ax/2 - b.x decreases)
+    op, mesh, grid, dirich = build(5, 7, 18)
+    try:
+        b = torch.from_numpy(synth.rhs_uniform(mesh.nglobal, 0, dirichlet=mesh.boundary)).cuda()
+        energies = []
+        for k in (2, 5, 12):
+            x, st = op.pcg_solve(b, maxit=k, fixed_iters=True)
+            ax = op.apply(STIFF, x)
+            true = ((b - ax).norm() / b.norm()).item()
+            assert abs(true - st["rel_res"][0]) <= 1e-9 * true, (k, true, st["rel_res"][0])
+            energies.append(0.5 * torch.dot(x, ax).item() - torch.dot(b, x).item())
+        assert energies[0] > energies[1] > energies[2], energies
+    finally:
+        op.close()
+
+
 def test_mixed_precision_e64cube_manufactured():
     import paper_2004_06722_amd.bp as B
     op, mesh, grid, dirich = build(5, 7, 18, fp32=True)
