@@ -148,6 +148,34 @@ def calib_copy():
     print(f"calib-copy: {n * 8} bytes read and written per launch, 3 launches")
 
 
+def workload_stream(args):
+    """Achievable HBM bandwidth on this device: STREAM-style copy (a = b) and
+    triad (a = b + s c) over 2 GiB FP64 vectors with torch's kernels, the
+    ceiling against which the streaming kernels of the iteration are read."""
+    import torch
+    n = 1 << 28
+    a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.full_like(a, 2.0)
+    out = {}
+    for name, fn, words in (("copy", lambda: a.copy_(b), 2),
+                            ("triad", lambda: torch.add(b, c, alpha=0.5, out=a), 3)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "GBs": words * 8 * n / (ms * 1e-3) / 1e9, "bytes": words * 8 * n}
+        log(f"{name}: {ms:.3f} ms per launch, {out[name]['GBs']:.0f} GB/s")
+    return {"workload": "STREAM-style copy and triad, 2^28 FP64 words per vector, 20 timed "
+                        "launches after 3 warm-up launches, HIP events", "results": out}
+
+
 def n08_from_sweep(points):
     """r_max, n_0.8 (log-interpolated first crossing of 0.8 r_max), t_0.8."""
     pts = sorted(points)
@@ -489,7 +517,8 @@ def main():
     ap.add_argument("--bk", type=int, default=5, choices=[1, 3, 5],
                     help="bk workload: which bake-off kernel")
     ap.add_argument("--workload", default="bp5",
-                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13", "bk", "helmholtz"],
+                    choices=["bp5", "vector", "mixed", "adjoint", "sweep13", "bk", "helmholtz",
+                             "stream"],
                     help="bp5: the headline line; the others print their own record")
     args = ap.parse_args()
     if args.calib_copy:
@@ -500,7 +529,7 @@ def main():
         torch.cuda.set_device(0)
         fn = {"vector": workload_vector, "mixed": workload_mixed, "adjoint": workload_adjoint,
               "sweep13": workload_sweep13, "bk": workload_bk,
-              "helmholtz": workload_helmholtz}[args.workload]
+              "helmholtz": workload_helmholtz, "stream": workload_stream}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     if args.gpus != 1:
