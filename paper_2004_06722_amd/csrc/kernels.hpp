@@ -18,14 +18,30 @@
 
 namespace bp {
 
+// Elements per work-group for planes of n threads: the count up to 256
+// threads that leaves the fewest idle lanes in the whole waves it occupies
+// (the smaller count on ties), e.g. 5 planes of 7 x 7 in 256 threads.
+constexpr int plane_elements(int n) {
+  int best = 1, best_used = n, best_threads = ((n + 63) / 64) * 64;
+  for (int e = 2; e * n <= 256; ++e) {
+    const int used = e * n, threads = ((used + 63) / 64) * 64;
+    if ((long)used * best_threads > (long)best_used * threads) {
+      best = e;
+      best_used = used;
+      best_threads = threads;
+    }
+  }
+  return best;
+}
+
 // Thread plane of an element: M x M threads, M = max(p1, q); EPB elements per
-// work-group so that small orders still fill a wave; THREADS rounded up to
-// whole waves (idle lanes take part in barriers and reductions only).
+// work-group (plane_elements); THREADS rounded up to whole waves (idle lanes
+// take part in barriers and reductions only).
 template <int P1, int Q>
 struct Plane {
   static constexpr int M = P1 > Q ? P1 : Q;
   static constexpr int N = M * M;
-  static constexpr int EPB = N >= 64 ? 1 : 64 / N;
+  static constexpr int EPB = plane_elements(N);
   static constexpr int USED = EPB * N;
   static constexpr int THREADS = ((USED + 63) / 64) * 64;
 };

@@ -10,8 +10,7 @@ namespace bp {
 // Gauss-Legendre values mirror GLPlane, the GLL ones Plane.
 int64_t plane_epb(int p1, int q, int which) {
   if (q > p1) return gl_epb(p1, q, which == BP_MASS ? kGLMass : kGLStiff);
-  const int n = p1 * p1;
-  return n >= 64 ? 1 : 64 / n;
+  return plane_elements(p1 * p1);
 }
 
 int64_t apply_rows(const bp_op_s *op, int which) {
