@@ -423,11 +423,13 @@ __global__ __launch_bounds__(kVecThreads) void k_sr_init(int64_t n, const T *__r
 }
 
 // p = u + beta p; s = w + beta s; x += alpha p; r -= alpha s; u = dinv r;
-// w = 0; partials r.u and r.r
-template <typename T>
+// w = 0; partials r.u and r.r. Only u is kept: r = u / dinv (0 on Dirichlet
+// nodes, where dinv = 0), so the pass moves 11 vector words per DOF; NT
+// streams vectors larger than the last-level cache (see ld_v).
+template <typename T, bool NT>
 __global__ __launch_bounds__(kVecThreads) void k_sr_update(
-    int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ u, T *__restrict__ w,
-    T *__restrict__ p, T *__restrict__ sv, const T *__restrict__ dinv, double *__restrict__ part,
+    int64_t n, T *__restrict__ x, T *__restrict__ u, T *__restrict__ w, T *__restrict__ p,
+    T *__restrict__ sv, const T *__restrict__ dinv, double *__restrict__ part,
     const DevScalars *__restrict__ sc) {
   if (sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
@@ -436,16 +438,17 @@ __global__ __launch_bounds__(kVecThreads) void k_sr_update(
   if (v < n) {
     const int64_t f = comp * n + v;
     const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
-    const T pv = u[f] + be * p[f];
-    const T s = w[f] + be * sv[f];
-    p[f] = pv;
-    sv[f] = s;
-    x[f] += al * pv;
-    const T rv = r[f] - al * s;
-    const T uv = dinv[v] * rv;
-    r[f] = rv;
-    u[f] = uv;
-    w[f] = T(0);
+    const T di = ld_v<NT>(dinv + v);
+    const T uo = ld_v<NT>(u + f);
+    const T pv = uo + be * ld_v<NT>(p + f);
+    const T s = ld_v<NT>(w + f) + be * ld_v<NT>(sv + f);
+    st_v<NT>(p + f, pv);
+    st_v<NT>(sv + f, s);
+    st_v<NT>(x + f, ld_v<NT>(x + f) + al * pv);
+    const T rv = (di != T(0) ? uo / di : T(0)) - al * s;
+    const T uv = di * rv;
+    st_v<NT>(u + f, uv);
+    st_v<NT>(w + f, T(0));
     ru = (double)rv * (double)uv;
     rr = (double)rv * (double)rv;
   }
@@ -733,10 +736,14 @@ void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const
 }
 
 template <typename T>
-void sr_update(int nc, int64_t n, T *x, T *r, T *u, T *w, T *p, T *sv, const T *dinv,
-               double *part, DevScalars *sc, hipStream_t s) {
-  hipLaunchKernelGGL((k_sr_update<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, x, r,
-                     u, w, p, sv, dinv, part, sc);
+void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
+               DevScalars *sc, hipStream_t s) {
+  if (n * (int64_t)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_sr_update<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
+                       n, x, u, w, p, sv, dinv, part, sc);
+  else
+    hipLaunchKernelGGL((k_sr_update<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
+                       n, x, u, w, p, sv, dinv, part, sc);
 }
 
 template <int NC>
@@ -771,7 +778,7 @@ void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba
 template void sr_init<double>(int, int64_t, const double *, double *, double *, double *,
                               double *, double *, const double *, double *, hipStream_t);
 template void sr_update<double>(int, int64_t, double *, double *, double *, double *, double *,
-                                double *, const double *, double *, DevScalars *, hipStream_t);
+                                const double *, double *, DevScalars *, hipStream_t);
 
 template <typename T>
 void cg_restart(int nc, int64_t n, T *r, T *p, const T *dinv, double *part,
