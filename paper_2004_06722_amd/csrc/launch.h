@@ -29,7 +29,8 @@ int launch_grad_kappa(const bp_op_s *op, const double *lam, const double *u, dou
                       hipStream_t s);
 
 // vector kernels (vec.hip); sizes are global nodes n and components nc
-// CG vector kernels run one node per thread (vec_blocks); fills and
+// CG vector kernels give each work-group kVecThreads nodes (vec_blocks; FP32
+// iteration kernels two per thread, FP64 one); fills and
 // conversions use a capped grid-stride grid (grid_blocks). Up to
 // kDirectRows block partial sums go straight to the final fixed-order
 // single-work-group sum (one launch less per reduction on small meshes);

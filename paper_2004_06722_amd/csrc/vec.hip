@@ -129,12 +129,23 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
     x[i] = v;
 }
 
-// The CG kernels run one node per thread over a 2D grid: blockIdx.y is the
-// component (vectors are component-major, [nc][n]). A work-group writes its
-// partial sum into row blockIdx.x, column (quantity * nc + component), of a
-// [gridDim.x][q * nc] table; every entry is written by exactly one group.
+// The CG kernels run over a 2D grid: blockIdx.y is the component (vectors
+// are component-major, [nc][n]) and work-group x covers nodes
+// [256 x, 256 x + 256). A work-group writes its partial sum into row
+// blockIdx.x, column (quantity * nc + component), of a [gridDim.x][q * nc]
+// table; every entry is written by exactly one group.
+//
+// The iteration kernels give an FP32 thread two nodes of its group's 256
+// (v and v + 128, 128 threads): a wave then has as many bytes in flight as
+// an FP64 wave with one node per thread, and the partial tables keep one row
+// per 256 nodes whatever the precision.
+template <typename T>
+constexpr int kNodesPerThread = sizeof(T) == 4 ? 2 : 1;
+template <typename T>
+constexpr int kGroupThreads = kVecThreads / kNodesPerThread<T>;
+template <int TH = kVecThreads>
 __device__ __forceinline__ void block_partial1(double v, double *part, int width, int col) {
-  constexpr int NW = kVecThreads / 64;
+  constexpr int NW = TH / 64;
   __shared__ double red[NW];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -233,26 +244,42 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
 // check = 0 (a fixed number of iterations): no early exit on the done flag,
 // so the loads do not wait for it (likewise in the other iteration kernels).
 template <typename T, bool NT>
-__global__ __launch_bounds__(kVecThreads) void k_cg_update_r(
+__global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r(
     int64_t n, T *__restrict__ z, T *__restrict__ w, const T *__restrict__ dinv,
     double *__restrict__ part, const DevScalars *__restrict__ sc, int check) {
+  constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
   if (check && sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
-  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
-  if (v < n) {
-    const int64_t f = comp * n + v;
-    const T al = (T)sc->alpha[comp];
-    const T di = ld_v<NT>(dinv + v);
-    const T zv = ld_v<NT>(z + f) - (al * di) * ld_v<NT>(w + f);
-    st_v<NT>(z + f, zv);
-    st_v<NT>(w + f, T(0));
-    const T rv = di != T(0) ? zv / di : T(0);
-    rz = (double)rv * (double)zv;
-    rr = (double)rv * (double)rv;
+  const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const T al = (T)sc->alpha[comp];
+  // all loads of the thread first, then the updates and stores
+  T di[K], zo[K], wo[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    di[j] = zo[j] = wo[j] = T(0);
+    if (v < n) {
+      di[j] = ld_v<NT>(dinv + v);
+      zo[j] = ld_v<NT>(z + comp * n + v);
+      wo[j] = ld_v<NT>(w + comp * n + v);
+    }
   }
-  block_partial1(rz, part, 2 * nc, comp);
-  block_partial1(rr, part, 2 * nc, nc + comp);
+  double rz = 0.0, rr = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    if (v < n) {
+      const int64_t f = comp * n + v;
+      const T zv = zo[j] - (al * di[j]) * wo[j];
+      st_v<NT>(z + f, zv);
+      st_v<NT>(w + f, T(0));
+      const T rv = di[j] != T(0) ? zv / di[j] : T(0);
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  block_partial1<TH>(rz, part, 2 * nc, comp);
+  block_partial1<TH>(rr, part, 2 * nc, nc + comp);
 }
 
 template <int NC>
@@ -281,19 +308,36 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restri
 // done is seen) stops the x update in the launches queued after the last
 // iteration.
 template <typename T, bool NT>
-__global__ __launch_bounds__(kVecThreads) void k_cg_update_xp(int64_t n, T *__restrict__ x,
-                                                              T *__restrict__ p,
-                                                              const T *__restrict__ z,
-                                                              const DevScalars *__restrict__ sc,
-                                                              int check) {
+__global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_xp(int64_t n, T *__restrict__ x,
+                                                                  T *__restrict__ p,
+                                                                  const T *__restrict__ z,
+                                                                  const DevScalars *__restrict__ sc,
+                                                                  int check) {
+  constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
   if (check && sc->halted) return;
-  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-  if (v < n) {
-    const int comp = blockIdx.y;
-    const int64_t f = comp * n + v;
-    const T pv = ld_v<NT>(p + f);
-    st_v<NT>(x + f, ld_v<NT>(x + f) + (T)sc->alpha[comp] * pv);
-    if (!sc->done) st_v<NT>(p + f, ld_v<NT>(z + f) + (T)sc->beta[comp] * pv);
+  const int comp = blockIdx.y;
+  const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
+  const bool dir = !sc->done;
+  T pv[K], xv[K], zv[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    pv[j] = xv[j] = zv[j] = T(0);
+    if (v < n) {
+      pv[j] = ld_v<NT>(p + comp * n + v);
+      xv[j] = ld_v<NT>(x + comp * n + v);
+      if (dir) zv[j] = ld_v<NT>(z + comp * n + v);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    if (v < n) {
+      const int64_t f = comp * n + v;
+      st_v<NT>(x + f, xv[j] + al * pv[j]);
+      if (dir) st_v<NT>(p + f, zv[j] + be * pv[j]);
+    }
   }
 }
 
@@ -427,33 +471,51 @@ __global__ __launch_bounds__(kVecThreads) void k_sr_init(int64_t n, const T *__r
 // nodes, where dinv = 0), so the pass moves 11 vector words per DOF; NT
 // streams vectors larger than the last-level cache (see ld_v).
 template <typename T, bool NT>
-__global__ __launch_bounds__(kVecThreads) void k_sr_update(
+__global__ __launch_bounds__(kGroupThreads<T>) void k_sr_update(
     int64_t n, T *__restrict__ x, T *__restrict__ u, T *__restrict__ w, T *__restrict__ p,
     T *__restrict__ sv, const T *__restrict__ dinv, double *__restrict__ part,
     const DevScalars *__restrict__ sc) {
+  constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
   if (sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
-  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-  double ru = 0.0, rr = 0.0;
-  if (v < n) {
-    const int64_t f = comp * n + v;
-    const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
-    const T di = ld_v<NT>(dinv + v);
-    const T uo = ld_v<NT>(u + f);
-    const T pv = uo + be * ld_v<NT>(p + f);
-    const T s = ld_v<NT>(w + f) + be * ld_v<NT>(sv + f);
-    st_v<NT>(p + f, pv);
-    st_v<NT>(sv + f, s);
-    st_v<NT>(x + f, ld_v<NT>(x + f) + al * pv);
-    const T rv = (di != T(0) ? uo / di : T(0)) - al * s;
-    const T uv = di * rv;
-    st_v<NT>(u + f, uv);
-    st_v<NT>(w + f, T(0));
-    ru = (double)rv * (double)uv;
-    rr = (double)rv * (double)rv;
+  const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
+  T di[K], uo[K], po[K], wo[K], so[K], xo[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    di[j] = uo[j] = po[j] = wo[j] = so[j] = xo[j] = T(0);
+    if (v < n) {
+      const int64_t f = comp * n + v;
+      di[j] = ld_v<NT>(dinv + v);
+      uo[j] = ld_v<NT>(u + f);
+      po[j] = ld_v<NT>(p + f);
+      wo[j] = ld_v<NT>(w + f);
+      so[j] = ld_v<NT>(sv + f);
+      xo[j] = ld_v<NT>(x + f);
+    }
   }
-  block_partial1(ru, part, 2 * nc, comp);
-  block_partial1(rr, part, 2 * nc, nc + comp);
+  double ru = 0.0, rr = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    if (v < n) {
+      const int64_t f = comp * n + v;
+      const T pn = uo[j] + be * po[j];
+      const T s = wo[j] + be * so[j];
+      st_v<NT>(p + f, pn);
+      st_v<NT>(sv + f, s);
+      st_v<NT>(x + f, xo[j] + al * pn);
+      const T rv = (di[j] != T(0) ? uo[j] / di[j] : T(0)) - al * s;
+      const T uv = di[j] * rv;
+      st_v<NT>(u + f, uv);
+      st_v<NT>(w + f, T(0));
+      ru += (double)rv * (double)uv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  block_partial1<TH>(ru, part, 2 * nc, comp);
+  block_partial1<TH>(rr, part, 2 * nc, nc + comp);
 }
 
 // first: gamma, r.r, b.b from the vector pass, delta = (u, A u) from the
@@ -692,11 +754,11 @@ template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
                  hipStream_t s, bool check) {
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
-    hipLaunchKernelGGL((k_cg_update_r<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
-                       n, r, w, dinv, part, sc, check ? 1 : 0);
+    hipLaunchKernelGGL((k_cg_update_r<T, true>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0);
   else
-    hipLaunchKernelGGL((k_cg_update_r<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
-                       n, r, w, dinv, part, sc, check ? 1 : 0);
+    hipLaunchKernelGGL((k_cg_update_r<T, false>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0);
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
@@ -711,11 +773,11 @@ template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
                   bool check) {
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
-    hipLaunchKernelGGL((k_cg_update_xp<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0,
-                       s, n, x, p, z, sc, check ? 1 : 0);
+    hipLaunchKernelGGL((k_cg_update_xp<T, true>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, x, p, z, sc, check ? 1 : 0);
   else
-    hipLaunchKernelGGL((k_cg_update_xp<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0,
-                       s, n, x, p, z, sc, check ? 1 : 0);
+    hipLaunchKernelGGL((k_cg_update_xp<T, false>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, x, p, z, sc, check ? 1 : 0);
 }
 
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
@@ -739,11 +801,11 @@ template <typename T>
 void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
                DevScalars *sc, hipStream_t s) {
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
-    hipLaunchKernelGGL((k_sr_update<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
-                       n, x, u, w, p, sv, dinv, part, sc);
+    hipLaunchKernelGGL((k_sr_update<T, true>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc);
   else
-    hipLaunchKernelGGL((k_sr_update<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s,
-                       n, x, u, w, p, sv, dinv, part, sc);
+    hipLaunchKernelGGL((k_sr_update<T, false>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc);
 }
 
 template <int NC>
