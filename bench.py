@@ -222,8 +222,12 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0, helm_beta=None):
     E, n = info["E"], info["n"]
     log(f"BP{bp} N={N} E={E} ncomp={ncomp}: {steps} iterations in {wall * 1e3:.1f} ms")
     apply_ms = st["apply_ms"] / max(st["apply_count"], 1)
-    ab = (model.apply_bytes(bp, N, E, ncomp) if helm_beta is None
-          else model.helm_apply_bytes(bp, N, E, ncomp))
+    if helm_beta is not None:
+        ab = model.helm_apply_bytes(bp, N, E, ncomp)
+    elif bp in (1, 2):   # the timed launch is the element kernel (w_L out, no assembly)
+        ab = model.mass_element_bytes(N, E, ncomp)
+    else:
+        ab = model.apply_bytes(bp, N, E, ncomp)
     return {"bp": bp, "helm_beta": helm_beta, "N": N, "E": E, "ncomp": ncomp, "n": n,
             "n_unique": info["n_unique"],
             "iters": steps, "wall_ms": wall * 1e3, "ms_per_iter": wall * 1e3 / steps,

@@ -86,6 +86,11 @@ int bp_rule(int n, int quad, double *x, double *w);
  *     NULL (no Dirichlet nodes, e.g. BP1/BP2 with Neumann conditions).
  *   flags: 0 or BP_SETUP_FP32.
  *   stream: stream for the uploads; bp_setup synchronises it before return.
+ * With GL quadrature (and nelem p1^3 < 2^31) the operator also holds the
+ * transposed gather map (int32, nglobal + 1 offsets and nelem p1^3 slots) and
+ * an element-local output buffer of ncomp nelem p1^3 words (per precision):
+ * the mass operator stores B_L u_L per element and assembles Q^T of it by a
+ * fixed-order gather, so its results do not depend on scheduling.
  * Errors: BP_ERR_ARG (ranges), BP_ERR_MESH (Jacobian <= 0 at a quadrature
  * point -- the message names the element -- or an id out of range),
  * BP_ERR_OOM, BP_ERR_HIP. On error *out is set to NULL.

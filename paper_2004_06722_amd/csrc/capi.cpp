@@ -65,6 +65,10 @@ void release(bp_op op) {
   dfree(op->part);
   dfree(op->tmp);
   dfree(op->sv);
+  dfree(op->tr_off);
+  dfree(op->tr_pos);
+  dfree(op->wl);
+  dfree(op->wl32);
   dfree(op->r32);
   dfree(op->p32);
   dfree(op->w32);
@@ -205,6 +209,12 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   // then skip the done flag (nothing waits on loading it)
   const bool check = !fixed;
   const int *done = check ? &op->sc->done : nullptr;
+  // mass on Gauss-Legendre points: the kernel stores w_L and the residual
+  // update gathers w = Q^T w_L itself (w stays zero)
+  const bool mass_wl = which == BP_MASS && op->tr_off != nullptr;
+  const int64_t nl = op->nelem * op->p1 * op->p1 * op->p1;
+  const T *wl = reinterpret_cast<const T *>(sizeof(T) == 4 ? (const void *)op->wl32
+                                                           : (const void *)op->wl);
   if (op->time_apply && op->apply_ev.empty()) {
     op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
     for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
@@ -214,11 +224,16 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
     for (int c = 0; c < chunk; ++c) {
       const bool tm = op->time_apply && timed < kMaxTimedApplies;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
-      rc = launch_apply(op, which, f32, p, w, masked, op->part, done, s);
+      rc = mass_wl ? launch_mass_wl(op, f32, p, masked, op->part, done, s)
+                   : launch_apply(op, which, f32, p, w, masked, op->part, done, s);
       if (rc) return rc;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
       cg_fin_alpha(nc, op->part, nb_apply, op->sc, s, check);
-      cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s, check);
+      if (mass_wl)
+        cg_update_r_gather<T>(nc, n, nl, r, wl, op->tr_off, op->tr_pos, dinv, op->part, op->sc,
+                              s, check);
+      else
+        cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s, check);
       cg_fin_beta(nc, nb_vec, op->part, op->sc, s, check);
       cg_update_xp<T>(nc, n, x, p, r, op->sc, s, check);
     }
@@ -510,6 +525,27 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRY(dmalloc(&op->idx, idx.size()));
   TRYHIP(hipMemcpyAsync(op->idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   TRYHIP(hipStreamSynchronize(s));
+  // Gauss-Legendre operators: the transposed gather map (counting sort of the
+  // element-local slots by global node, ascending within a node) for the
+  // mass operator's fixed-order assembly, and its element-local output
+  const int64_t nl = nelem * n3;
+  if (!op->colloc && nl < (int64_t(1) << 31)) {
+    std::vector<int32_t> off((size_t)nglobal + 1, 0), pos((size_t)nl);
+    for (int64_t k = 0; k < nl; ++k) ++off[(size_t)elem_dofs[k] + 1];
+    for (int64_t g = 0; g < nglobal; ++g) off[(size_t)g + 1] += off[(size_t)g];
+    {
+      std::vector<int32_t> cur(off.begin(), off.end() - 1);
+      for (int64_t k = 0; k < nl; ++k) pos[(size_t)cur[(size_t)elem_dofs[k]]++] = (int32_t)k;
+    }
+    TRY(dmalloc(&op->tr_off, off.size()));
+    TRY(dmalloc(&op->tr_pos, pos.size()));
+    TRY(dmalloc(&op->wl, nl * ncomp));
+    TRYHIP(hipMemcpyAsync(op->tr_off, off.data(), off.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    TRYHIP(hipMemcpyAsync(op->tr_pos, pos.data(), pos.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    TRYHIP(hipStreamSynchronize(s));
+  }
   TRY(upload_basis(op, s));
 
   // geometric factors of eq. (gij) and B~ of eq. (mass), computed on the device
@@ -566,6 +602,7 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
     TRY(dmalloc(&op->x32, nv));
     TRY(dmalloc(&op->b32, nv));
     TRY(dmalloc(&op->dinv32, nglobal));
+    if (op->tr_off) TRY(dmalloc(&op->wl32, nl * ncomp));
   }
 #undef TRY
 #undef TRYHIP

@@ -331,7 +331,13 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
 // index reversed, [a][b][c] with c fastest, so that the stage-3 pencils,
 // adjacent lanes along (b, c), read them coalesced; G and the gather map are
 // requested at entry. One component per launch (u and w point at component
-// c0). With LOCAL the result is stored per element.
+// c0). With LOCAL the input is read and the result stored per element. With
+// WL the input is gathered from the global vector and the element result
+// w_L is stored per element ([E][p1^3], zero at skipped nodes) instead of
+// scatter-added: the mass operator moves little quadrature data, so FP64
+// atomics bound it, and the assembly Q^T w_L is then done as a fixed-order
+// gather over the transposed map (by the residual update of the PCG, or by
+// a gather kernel after the launch).
 // ---------------------------------------------------------------------------
 enum GLMode { kGLMass = 0, kGLStiff = 1, kGLHelm = 2 };
 
@@ -450,7 +456,7 @@ struct GLPlane {
   static constexpr int THREADS = ((USED + 63) / 64) * 64;
 };
 
-template <int P1, int Q, typename T, int MODE, bool LOCAL = false>
+template <int P1, int Q, typename T, int MODE, bool LOCAL = false, bool WL = false>
 __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
     const T *__restrict__ Bb, const T *__restrict__ basis, const T *__restrict__ u,
@@ -698,13 +704,16 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
     T wk[P1];
     wz.get(wk);
 #pragma unroll
-    for (int k = 0; k < P1; ++k)
-      if (mb >> k & 1u) {
-        if constexpr (LOCAL)  // element-local output, one lane per entry: no assembly
-          w[gk[k]] = wk[k];
-        else
-          atomic_add(w + gk[k], wk[k]);
+    for (int k = 0; k < P1; ++k) {
+      if constexpr (LOCAL) {  // element-local output, one lane per entry: no assembly
+        if (mb >> k & 1u) w[gk[k]] = wk[k];
+      } else if constexpr (WL) {
+        // w_L of the element (0 at skipped nodes); the caller applies Q^T
+        if (live) w[ec * N3 + ci + P1 * (cj + P1 * k)] = (mb >> k & 1u) ? wk[k] : T(0);
+      } else if (mb >> k & 1u) {
+        atomic_add(w + gk[k], wk[k]);
       }
+    }
   }
   double enb[1] = {en};
   if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + c0, 1);

@@ -16,6 +16,12 @@ int64_t apply_blocks(const bp_op_s *op);
 int64_t max_partial_rows(const bp_op_s *op);
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s);
+// mass element kernel with element-local output: op->wl (op->wl32 if f32)
+// [ncomp][nelem][p1^3] = B_L (Q u), zero at masked nodes; needs op->tr_off
+// (Gauss-Legendre operators). launch_apply(BP_MASS) runs it and then
+// gather_local; the PCG iteration fuses the gather into the residual update.
+int launch_mass_wl(const bp_op_s *op, bool f32, const void *u, bool masked, double *part,
+                   const int *done, hipStream_t s);
 // w_L = A_L u_L (or B_L u_L) per element, no gather or scatter; uL and wL are
 // [ncomp][nelem][p1^3] in the precision of f32
 int launch_apply_local(const bp_op_s *op, int which, bool f32, const void *uL, void *wL,
@@ -71,6 +77,19 @@ void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStre
 template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
                   bool check = true);
+
+// transposed gather Q^T w_L: w[c][g] += sum of wl[c][pos[k]] for k in
+// [off[g], off[g+1]) in ascending order (wl is [nc][nl]); skipped while
+// *done (done may be NULL)
+template <typename T>
+void gather_local(int nc, int64_t n, int64_t nl, const int32_t *off, const int32_t *pos,
+                  const T *wl, T *w, const int *done, hipStream_t s);
+// cg_update_r with w = Q^T w_L gathered per node (no w vector is read,
+// written or cleared)
+template <typename T>
+void cg_update_r_gather(int nc, int64_t n, int64_t nl, T *r, const T *wl, const int32_t *off,
+                        const int32_t *pos, const T *dinv, double *part, DevScalars *sc,
+                        hipStream_t s, bool check = true);
 
 // single-reduction PCG: init (r, u = dinv r, p = s = w = 0; partials r.u, r.r,
 // b.b), the fused vector update (partials r.u, r.r), and the finisher that

@@ -60,7 +60,8 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
   return BP_OK;
 }
 
-template <int P1, int Q, typename T, int MODE, bool LOCAL>
+// WL: u global, w element-local [ncomp][nelem][p1^3] (see k_op_gl)
+template <int P1, int Q, typename T, int MODE, bool LOCAL, bool WL = false>
 int gauss(const bp_op_s *op, const T *Gm, const T *Bb, const T *basis, const T *u, T *w,
           int masked, double *part, const int *done, hipStream_t s) {
   using PL = GLPlane<P1, Q, MODE>;
@@ -68,12 +69,28 @@ int gauss(const bp_op_s *op, const T *Gm, const T *Bb, const T *basis, const T *
   const int64_t grid = (op->nelem + PL::EPB - 1) / PL::EPB;
   if (grid != apply_rows(op, MODE == kGLMass ? BP_MASS : BP_STIFF))
     return set_error(BP_ERR_ARG, "plane layout");
-  const int64_t cs = vec_stride<LOCAL>(op);
+  const int64_t cs = vec_stride<LOCAL>(op), ws = WL ? vec_stride<true>(op) : cs;
   for (int c = 0; c < op->ncomp; ++c)
-    hipLaunchKernelGGL((k_op_gl<P1, Q, T, MODE, LOCAL>), dim3(grid), dim3(PL::THREADS), 0, s,
-                       op->nelem, op->idx, Gm, Bb, basis, u + c * cs, w + c * cs, op->ncomp, c,
-                       masked, part, done);
+    hipLaunchKernelGGL((k_op_gl<P1, Q, T, MODE, LOCAL, WL>), dim3(grid), dim3(PL::THREADS), 0,
+                       s, op->nelem, op->idx, Gm, Bb, basis, u + c * cs, w + c * ws, op->ncomp,
+                       c, masked, part, done);
   return BP_OK;
+}
+
+template <typename T>
+int dispatch_mass_wl(const bp_op_s *op, const T *Bt, const T *basis, const T *u, T *wl,
+                     int masked, double *part, const int *done, hipStream_t s) {
+  if (op->colloc || op->q != op->p1 + 1)
+    return set_error(BP_ERR_ARG, "element-local mass output needs Gauss-Legendre q = p + 2");
+#define BP_CASE(P) \
+  case P:          \
+    return gauss<P, P + 1, T, kGLMass, false, true>(op, Bt, nullptr, basis, u, wl, masked, part, \
+                                                    done, s);
+  switch (op->p1) {
+    BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
+  }
+#undef BP_CASE
+  return set_error(BP_ERR_ARG, "no compiled kernel for this (p, q, quadrature)");
 }
 
 // which = BP_HELM: H = A + B_beta (eq. (hm2)), the beta term fused into the
@@ -153,8 +170,37 @@ static int launch_apply_impl(const bp_op_s *op, int which, bool f32, const void 
   return BP_OK;
 }
 
+int launch_mass_wl(const bp_op_s *op, bool f32, const void *u, bool masked, double *part,
+                   const int *done, hipStream_t s) {
+  if (!op->tr_off) return set_error(BP_ERR_ARG, "no transposed gather map");
+  int rc;
+  if (f32)
+    rc = dispatch_mass_wl<float>(op, op->Bt32, op->basis32, (const float *)u, op->wl32, masked,
+                                 part, done, s);
+  else
+    rc = dispatch_mass_wl<double>(op, op->Bt, op->basis_d, (const double *)u, op->wl, masked,
+                                  part, done, s);
+  if (rc != BP_OK) return rc;
+  BP_HIP(hipGetLastError());
+  return BP_OK;
+}
+
 int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w, bool masked,
                  double *part, const int *done, hipStream_t s) {
+  if (which == BP_MASS && op->tr_off) {
+    // element kernel into w_L, then w += Q^T w_L by the transposed gather
+    const int rc = launch_mass_wl(op, f32, u, masked, part, done, s);
+    if (rc != BP_OK) return rc;
+    const int64_t nl = op->nelem * op->p1 * op->p1 * op->p1;
+    if (f32)
+      gather_local<float>(op->ncomp, op->nglobal, nl, op->tr_off, op->tr_pos, op->wl32,
+                          (float *)w, done, s);
+    else
+      gather_local<double>(op->ncomp, op->nglobal, nl, op->tr_off, op->tr_pos, op->wl,
+                           (double *)w, done, s);
+    BP_HIP(hipGetLastError());
+    return BP_OK;
+  }
   return launch_apply_impl<false>(op, which, f32, u, w, masked, part, done, s);
 }
 

@@ -282,6 +282,92 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r(
   block_partial1<TH>(rr, part, 2 * nc, nc + comp);
 }
 
+// Q^T w_L at one node: the sum of wc[pos[k]] over k in [k0, k1) in
+// ascending order. The first four contributions are requested together and
+// branch-free (two round trips: pos, then w_L; an index past the node's range
+// is clamped to the last slot nl - 1 and its value dropped); a conforming
+// hexahedral mesh gives every node 1, 2, 4 or 8, so only nodes shared by more
+// than four elements go round the loop. Dropped values add an exact zero, so
+// the order of the additions is that of the plain loop.
+template <typename T>
+__device__ __forceinline__ T gather_node(const T *__restrict__ wc,
+                                         const int32_t *__restrict__ pos, int32_t k0,
+                                         int32_t k1, int32_t last) {
+  int32_t ps[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) ps[m] = pos[min(k0 + m, last)];
+  T c[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) c[m] = wc[ps[m]];
+  T acc = T(0);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc += k0 + m < k1 ? c[m] : T(0);
+  for (int32_t k = k0 + 4; k < k1; ++k) acc += wc[pos[k]];
+  return acc;
+}
+
+// The same update with w = Q^T w_L formed per node from the element-local
+// output of the mass kernel: w_v is the sum of wl[pos[k]] over
+// k in [off[v], off[v+1]) in ascending order, a fixed order, so the result
+// does not depend on scheduling as an atomic scatter does. No w vector is
+// read, written or cleared; the pass reads z, dinv, the two offsets, and
+// pos and w_L once per element-local slot.
+template <typename T, bool NT>
+__global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r_gather(
+    int64_t n, int64_t nl, T *__restrict__ z, const T *__restrict__ wl,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ pos,
+    const T *__restrict__ dinv, double *__restrict__ part, const DevScalars *__restrict__ sc,
+    int check) {
+  constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
+  if (check && sc->done) return;
+  const int comp = blockIdx.y, nc = gridDim.y;
+  const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const T al = (T)sc->alpha[comp];
+  const T *wc = wl + comp * nl;
+  T di[K], zo[K], wv[K];
+  int32_t o0[K], o1[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    di[j] = zo[j] = wv[j] = T(0);
+    o0[j] = o1[j] = 0;
+    if (v < n) {  // the offsets first: the gather waits only for them
+      o0[j] = off[v];
+      o1[j] = off[v + 1];
+      di[j] = ld_v<NT>(dinv + v);
+      zo[j] = ld_v<NT>(z + comp * n + v);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) wv[j] = gather_node(wc, pos, o0[j], o1[j], (int32_t)(nl - 1));
+  double rz = 0.0, rr = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * TH;
+    if (v < n) {
+      const T zv = zo[j] - (al * di[j]) * wv[j];
+      st_v<NT>(z + comp * n + v, zv);
+      const T rv = di[j] != T(0) ? zv / di[j] : T(0);
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+    }
+  }
+  block_partial1<TH>(rz, part, 2 * nc, comp);
+  block_partial1<TH>(rr, part, 2 * nc, nc + comp);
+}
+
+// w[c][v] += Q^T w_L at node v (fixed order as above), one node per thread
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_gather_local(
+    int64_t n, int64_t nl, const int32_t *__restrict__ off, const int32_t *__restrict__ pos,
+    const T *__restrict__ wl, T *__restrict__ w, const int *__restrict__ done) {
+  if (done && *done) return;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v >= n) return;
+  const T *wc = wl + blockIdx.y * nl;
+  w[blockIdx.y * n + v] += gather_node(wc, pos, off[v], off[v + 1], (int32_t)(nl - 1));
+}
+
 template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restrict__ part,
                                                           int64_t nb, DevScalars *sc, int check) {
@@ -780,6 +866,27 @@ void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hip
                        dim3(kGroupThreads<T>), 0, s, n, x, p, z, sc, check ? 1 : 0);
 }
 
+template <typename T>
+void gather_local(int nc, int64_t n, int64_t nl, const int32_t *off, const int32_t *pos,
+                  const T *wl, T *w, const int *done, hipStream_t s) {
+  hipLaunchKernelGGL((k_gather_local<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, nl,
+                     off, pos, wl, w, done);
+}
+
+template <typename T>
+void cg_update_r_gather(int nc, int64_t n, int64_t nl, T *r, const T *wl, const int32_t *off,
+                        const int32_t *pos, const T *dinv, double *part, DevScalars *sc,
+                        hipStream_t s, bool check) {
+  if (n * (int64_t)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_cg_update_r_gather<T, true>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, nl, r, wl, off, pos, dinv, part, sc,
+                       check ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_cg_update_r_gather<T, false>), dim3(vec_blocks(n), nc),
+                       dim3(kGroupThreads<T>), 0, s, n, nl, r, wl, off, pos, dinv, part, sc,
+                       check ? 1 : 0);
+}
+
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
                  double *part, DevScalars *sc, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
@@ -874,5 +981,15 @@ template void cg_update_xp<double>(int, int64_t, double *, double *, const doubl
                                    DevScalars *, hipStream_t, bool);
 template void cg_update_xp<float>(int, int64_t, float *, float *, const float *, DevScalars *,
                                   hipStream_t, bool);
+template void gather_local<double>(int, int64_t, int64_t, const int32_t *, const int32_t *,
+                                   const double *, double *, const int *, hipStream_t);
+template void gather_local<float>(int, int64_t, int64_t, const int32_t *, const int32_t *,
+                                  const float *, float *, const int *, hipStream_t);
+template void cg_update_r_gather<double>(int, int64_t, int64_t, double *, const double *,
+                                         const int32_t *, const int32_t *, const double *,
+                                         double *, DevScalars *, hipStream_t, bool);
+template void cg_update_r_gather<float>(int, int64_t, int64_t, float *, const float *,
+                                        const int32_t *, const int32_t *, const float *, double *,
+                                        DevScalars *, hipStream_t, bool);
 
 }  // namespace bp

@@ -36,6 +36,16 @@ def apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
         + word * VECTOR_WORDS_OPERATOR * n * ncomp
 
 
+def mass_element_bytes(p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
+    """Bytes of the Gauss-Legendre mass kernel as the PCG runs it for BP1/BP2:
+    B~ + map + u gathered (one word per DOF) + w_L stored per element
+    ((p+1)^3 words per element and component). The assembly Q^T w_L is done by
+    the residual update, so these are the bytes of the timed operator launch;
+    the iteration counts keep the algorithmic operator bytes of apply_bytes."""
+    return E * (word * geometry_words(1, p) + 4 * (p + 1) ** 3) \
+        + word * ncomp * (p ** 3 * E + E * (p + 1) ** 3)
+
+
 def helm_apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
     """Bytes of one Helmholtz application H = A + B_beta (eq. (hm2)) read once:
     the stiffness application plus beta B~ (q^3 words per element)."""

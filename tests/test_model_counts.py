@@ -1,0 +1,39 @@
+"""Pins of the algorithmic byte and flop counts that bench.py divides by the
+measured times (the roofline fractions): per-element figures of section 5
+worked out by hand at N = 7."""
+import pytest
+
+from paper_2004_06722_amd import model
+
+
+def test_bk5_per_element_counts_at_n7():
+    # collocated GLL, q = p1 = 8: six G words per point (eq. (gij)), 512 points
+    assert model.geometry_words(5, 7) == 6 * 512
+    # J^ = I: three derivative contractions and their transposes,
+    # 6 x 2 p1^4, plus 15 flops per point for G (u_r, u_s, u_t)
+    assert model.apply_flops_per_element(5, 7) == 12 * 8 ** 4 + 15 * 8 ** 3 == 56832
+    # one element's operator: 24,576 B of G + 2,048 B of int32 map + u in,
+    # w out (two words per DOF, 343 DOFs per element)
+    assert model.apply_bytes(5, 7, 1) == 24576 + 2048 + 2 * 8 * 343
+    # a PCG iteration adds ten vector words per DOF
+    assert model.iteration_bytes(5, 7, 1) == model.apply_bytes(5, 7, 1) + 10 * 8 * 343
+
+
+def test_bp1_counts_at_n7():
+    # Gauss-Legendre q = p + 2 = 9: one B~ word per point (eq. (mass))
+    assert model.geometry_words(1, 7) == 9 ** 3
+    assert model.apply_bytes(1, 7, 1) == 8 * 729 + 4 * 512 + 2 * 8 * 343
+    # the mass kernel as the PCG runs it: u gathered (343 words), w_L stored
+    # per element slot (512 words) instead of w scatter-added
+    assert model.mass_element_bytes(7, 1) == 8 * 729 + 4 * 512 + 8 * (343 + 512) == 14720
+    assert model.mass_element_bytes(7, 10, ncomp=3) == \
+        10 * (8 * 729 + 4 * 512) + 3 * 8 * 10 * (343 + 512)
+
+
+@pytest.mark.parametrize("p", [1, 3, 8])
+def test_mass_flops_reduce_to_the_tensor_form(p):
+    # 4 p1^4 (g^3 + g^2 + g) + q^3 with g = q / p1: the J^ chain there and
+    # back (three contractions each way, 2 flops per multiply-add) and B~
+    p1, q = p + 1, p + 2
+    chain = 2 * 2 * (q * p1 ** 3 + q * q * p1 ** 2 + q ** 3 * p1)
+    assert model.apply_flops_per_element(1, p) == pytest.approx(chain + q ** 3)
