@@ -10,7 +10,7 @@ import pytest
 import synth
 from oracle import adjoint, mixed
 from oracle.assembled import assemble
-from oracle.operators import MASS, STIFF
+from oracle.operators import MASS, STIFF, Discretization
 from oracle.pcg import pcg
 from tests.gpu_cases import TOL, Case, rel
 
@@ -102,6 +102,37 @@ def test_fp32_apply_matches_single_precision_oracle():
         # contraction length, relative to the result's norm
         assert rel(w32, ref64) < 2e-6
         assert rel(w32, ref32) < 2e-6
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("p,ncomp", [(7, 1), (5, 2), (3, 3)])
+def test_fp32_stiffness_apply_components(p, ncomp):
+    # float32 rounding of G, D and the sums, relative to the result's norm
+    c = Case(6 if ncomp > 1 else 5, p, 3, 2, 2, seed=80 + p, ncomp=ncomp, fp32=True)
+    try:
+        u = c.vec(81).astype(np.float32)
+        w = host(c.op.apply(STIFF, dev(u)))
+        ref = c.disc.apply(STIFF, u.astype(np.float64))
+        if ncomp == 1:
+            assert rel(w, ref) < 2e-6
+        else:
+            for k in range(ncomp):
+                assert rel(w[:, k], ref[:, k]) < 2e-6
+    finally:
+        c.close()
+
+
+def test_fp32_stiffness_apply_with_kappa():
+    c = Case(5, 4, 3, 3, 2, seed=90, fp32=True)
+    try:
+        kap = synth.kappa_log(c.mesh.node_xyz, 91)
+        c.op.set_coeff(torch.tensor(kap, device="cuda"))
+        kd = Discretization(c.disc.rule, c.mesh.elem_dofs, c.mesh.node_xyz, c.disc.nglobal,
+                            c.dir, kappa=kap)
+        u = (c.vec(92) * (1 - c.mesh.boundary)).astype(np.float32)
+        w = host(c.op.apply(STIFF, dev(u)))
+        assert rel(w, kd.apply(STIFF, u.astype(np.float64))) < 2e-6
     finally:
         c.close()
 
