@@ -10,6 +10,7 @@ rounding of the factors and sums, relative to the result's norm)."""
 import numpy as np
 import pytest
 
+import synth
 from oracle.operators import MASS
 from oracle.pcg import pcg
 from tests.gpu_cases import TOL, Case, rel
@@ -91,3 +92,32 @@ def test_fp32_mass_apply_matches_oracle():
     finally:
         c.close()
 
+
+
+def test_mass_gather_with_unreferenced_nodes():
+    # nglobal may exceed the ids the elements use: the trailing nodes have an
+    # empty slot range (off[v] = off[v + 1] = nelem p1^3), read nothing that
+    # counts and get w = 0; the other nodes are unchanged
+    import paper_2004_06722_amd.bp as B
+    c = Case(1, 3, 2, 2, 2, seed=95)
+    try:
+        xi, _ = B.rule(4, B.GLL)
+        lm = synth.brick_mesh(2, 2, 2, 3, xi, 95)
+        n = c.disc.nglobal
+        with B.Operator(3, 5, B.GL, lm.elem_dofs, lm.node_xyz, n + 3) as op:
+            u = np.concatenate([c.vec(96), [1.0, -2.0, 3.0]])
+            w = host(op.apply(MASS, dev(u), masked=False))
+            assert np.all(w[n:] == 0.0)
+            assert rel(w[:n], c.disc.apply(MASS, u[:n], masked=False)) <= TOL
+            d = host(op.diag(MASS, masked=False))
+            assert np.all(d[n:] == 0.0)
+            x, st = op.pcg_solve(dev(u * np.r_[np.ones(n), np.zeros(3)]), which=MASS, maxit=4,
+                                 fixed_iters=True)
+            rec = []
+            pcg(lambda v: c.disc.apply(MASS, v, masked=False), u[:n],
+                c.disc.jacobi_inverse(MASS, masked=False), maxit=4, fixed_iters=True, record=rec)
+            xh = host(x)
+            assert np.all(xh[n:] == 0.0)
+            assert rel(xh[:n], rec[-1]) <= TOL
+    finally:
+        c.close()
