@@ -75,18 +75,6 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *out, in
     }
 }
 
-// Work-group barrier that also stops the instruction scheduler from moving
-// work across it. With one-wave work-groups the compiler drops s_barrier
-// (LDS accesses of a wave are ordered), and without the scheduling fence it
-// would hoist the LDS reads of every plane at once and run out of registers.
-// The memory clobber also makes the compiler re-read the lane-dependent
-// rows of D^ from LDS in every plane instead of keeping them all live.
-__device__ __forceinline__ void plane_sync() {
-  __syncthreads();
-  __asm__ volatile("" ::: "memory");
-  __builtin_amdgcn_sched_barrier(0);
-}
-
 // Decoded gather index: global id, or -1 when the node is skipped
 // (element slot not live, or a Dirichlet node under the mask).
 __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
@@ -102,11 +90,10 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // the G column in registers across several components doubles the register
 // footprint and halves occupancy, which costs more than re-reading G.
 //
-// The kernel is bound by HBM latency more than by arithmetic, so it is laid
-// out to need few dependent round trips: each lane requests its whole column
-// of G (6 x p1 values, GPRE planes of them at entry when GPRE = p1) and of
-// the gather map at once, then gathers u, then computes from registers and
-// LDS. The k direction stays in registers; the r and s contractions go
+// Arithmetic is not the limit (HBM traffic and the rate of the atomic
+// scatter are), so the kernel is laid out to need few dependent round trips:
+// each lane requests its whole column of G (6 x p1 values) and of the gather
+// map at entry, then gathers u, then computes from registers and LDS. The k direction stays in registers; the r and s contractions go
 // through LDS tiles. Loads are branch-free: an element slot past the end
 // reads the last element and a Dirichlet node reads its (valid) global
 // entry, both masked. Entries of D^ with compile-time indices
