@@ -234,7 +234,8 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
  *   BP_OPT_TIME_APPLY (value 0/1): bp_pcg_solve records a HIP event pair on
  *   its stream around every operator launch of the iteration loop (at most
  *   4096 pairs per solve) and reports their summed duration in
- *   bp_pcg_stats.apply_ms. Costs two event records per iteration.
+ *   bp_pcg_stats.apply_ms. Costs two event records per iteration; the events
+ *   are created when the option is first set (BP_ERR_HIP if that fails).
  * Unknown options return BP_ERR_ARG.
  */
 #define BP_OPT_TIME_APPLY 1
@@ -250,8 +251,8 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
  *       by recurrence, one fused vector pass and one reduction phase per
  *       iteration (three launches instead of five for small meshes; the
  *       iterates are those of the standard form up to rounding, section 3's
- *       Jacobi-PCG in exact arithmetic). Allocates one more vector on first
- *       use. */
+ *       Jacobi-PCG in exact arithmetic). Selecting it allocates one more
+ *       vector (BP_ERR_OOM if that fails); bp_pcg_solve allocates nothing. */
 #define BP_OPT_CG_VARIANT 3
 #define BP_CG_STANDARD 0
 #define BP_CG_SINGLE_REDUCTION 1

@@ -87,7 +87,7 @@ struct bp_op_s {
   bool time_apply = false;
   int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
   int cg_variant = 0;  // BP_CG_STANDARD or BP_CG_SINGLE_REDUCTION (bp_pcg_solve)
-  double *sv = nullptr;  // s = A p of the single-reduction PCG (allocated on first use)
+  double *sv = nullptr;  // s = A p of the single-reduction PCG (allocated when selected)
   // Gauss-Legendre operators: the gather map transposed (CSR over global
   // nodes: the element-local slots e p1^3 + l of node g are
   // tr_pos[tr_off[g] .. tr_off[g + 1]), ascending) and the element-local

@@ -215,10 +215,6 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   const int64_t nl = op->nelem * op->p1 * op->p1 * op->p1;
   const T *wl = reinterpret_cast<const T *>(sizeof(T) == 4 ? (const void *)op->wl32
                                                            : (const void *)op->wl);
-  if (op->time_apply && op->apply_ev.empty()) {
-    op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
-    for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
-  }
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
     for (int c = 0; c < chunk; ++c) {
@@ -300,10 +296,6 @@ int pcg_run_sr(bp_op op, int which, const double *b, double *x, const double *di
   // then skip the done flag (nothing waits on loading it)
   const bool check = !fixed;
   const int *done = check ? &op->sc->done : nullptr;
-  if (op->time_apply && op->apply_ev.empty()) {
-    op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
-    for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
-  }
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
     for (int c = 0; c < chunk; ++c) {
@@ -731,10 +723,6 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
   double apply_ms = 0.0;
   int apply_count = 0;
   if (op->cg_variant == BP_CG_SINGLE_REDUCTION) {
-    if (!op->sv) {
-      rc = dmalloc(&op->sv, op->nglobal * op->ncomp);
-      if (rc) return rc;
-    }
     rc = pcg_run_sr(op, which, b, x, op->dinv[dinv_slot(which)], rtol, maxit, fixed_iters != 0,
                     false, s, &iters, &ms, &apply_ms, &apply_count);
   } else {
@@ -831,13 +819,23 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g, void 
 
 int bp_set_option(bp_op op, int option, int value) {
   if (!op) return set_error(BP_ERR_ARG, "null operator");
+  // the resources an option needs are created here, so that the solves
+  // themselves allocate nothing
   if (option == BP_OPT_TIME_APPLY) {
+    if (value && op->apply_ev.empty()) {
+      op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
+      for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
+    }
     op->time_apply = value != 0;
     return BP_OK;
   }
   if (option == BP_OPT_CG_VARIANT) {
     if (value != BP_CG_STANDARD && value != BP_CG_SINGLE_REDUCTION)
       return set_error(BP_ERR_ARG, "bp_set_option: unknown CG variant");
+    if (value == BP_CG_SINGLE_REDUCTION && !op->sv) {
+      const int rc = dmalloc(&op->sv, op->nglobal * op->ncomp);
+      if (rc) return rc;
+    }
     op->cg_variant = value;
     return BP_OK;
   }

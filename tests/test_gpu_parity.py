@@ -163,6 +163,31 @@ def test_pcg_iterates_match_oracle_orders(bp, p, ncomp):
         c.close()
 
 
+
+@pytest.mark.parametrize("bp,p,sr", [(1, 4, False), (3, 3, False), (5, 5, False), (5, 3, True),
+                                      (1, 3, True)])
+def test_pcg_from_nonzero_initial_guess(bp, p, sr):
+    # x holds x0 on entry: the first residual is b - A x0 (the operator on x0
+    # before the loop; for BP1 the mass kernel and the stand-alone gather)
+    c = Case(bp, p, *grid_for(p), seed=31)
+    try:
+        c.op.set_cg_variant(sr)
+        which = MASS if bp == 1 else STIFF
+        masked = bp >= 3
+        mask = (1 - c.mesh.boundary) if masked else np.ones(c.disc.nglobal)
+        b = c.vec(32) * mask
+        x0 = c.vec(33) * mask
+        rec = []
+        pcg(lambda v: c.disc.apply(which, v, masked=masked), b,
+            c.disc.jacobi_inverse(which, masked=masked), x0=x0, maxit=5, fixed_iters=True,
+            record=rec)
+        for k in (1, 5):
+            x, st = c.op.pcg_solve(dev(b), x=dev(x0), which=which, maxit=k, fixed_iters=True)
+            assert st["iters"] == k
+            assert rel(host(x), rec[k - 1]) <= TOL, (k, rel(host(x), rec[k - 1]))
+    finally:
+        c.close()
+
 @pytest.mark.parametrize("bp,p,ncomp", [(5, 3, 1), (5, 7, 1), (5, 4, 3), (3, 5, 1), (1, 4, 1),
                                          (5, 1, 2)])
 def test_single_reduction_pcg_iterates_match_oracle(bp, p, ncomp):
