@@ -138,17 +138,20 @@ int check_op(bp_op op) {
 }
 
 // Inverse diagonal for `which` (cached; masked when the operator has Dirichlet nodes).
-int dinv_slot(int which) { return which == BP_STIFF ? 1 : (which == BP_HELM ? 2 : 0); }
+// Slots: 0 mass, 1 stiffness, 2 Helmholtz; without a beta term H = A uses
+// slot 1. Slots 0 and 1 are allocated by bp_setup, slot 2 by
+// bp_set_helmholtz, so the solves allocate nothing.
+int dinv_slot(const bp_op_s *op, int which) {
+  if (which == BP_MASS) return 0;
+  return which == BP_HELM && op->Bb ? 2 : 1;
+}
 
 bool valid_which(int which) { return which == BP_MASS || which == BP_STIFF || which == BP_HELM; }
 
 int ensure_dinv(bp_op op, int which, hipStream_t s) {
-  const int slot = dinv_slot(which);
+  const int slot = dinv_slot(op, which);
   if (op->dinv_valid[slot]) return BP_OK;
-  if (!op->dinv[slot]) {
-    int rc = dmalloc(&op->dinv[slot], op->nglobal);
-    if (rc) return rc;
-  }
+  if (!op->dinv[slot]) return set_error(BP_ERR_ARG, "inverse diagonal not allocated");
   fill_f64(op->tmp, op->nglobal, 0.0, s);
   int rc = launch_diag(op, which, op->tmp, op->has_dirichlet, s);
   if (rc) return rc;
@@ -569,6 +572,8 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
                                       std::to_string(bad_host));
     TRY(rc);
   }
+  TRY(dmalloc(&op->dinv[0], nglobal));
+  TRY(dmalloc(&op->dinv[1], nglobal));
   TRY(dmalloc(&op->r, nv));
   TRY(dmalloc(&op->pv, nv));
   TRY(dmalloc(&op->w, nv));
@@ -656,6 +661,10 @@ int bp_set_helmholtz(bp_op op, double beta, const double *beta_q, void *stream) 
         if (rc) return rc;
       }
     }
+    if (!op->dinv[2]) {
+      rc = dmalloc(&op->dinv[2], op->nglobal);
+      if (rc) return rc;
+    }
     scale_mass(op->Bt, beta_q, beta, op->Bb, op->Bb32, op->q * op->q * op->q,
                op->colloc ? 0 : op->q, count, s);
     BP_HIP(hipGetLastError());
@@ -723,10 +732,10 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
   double apply_ms = 0.0;
   int apply_count = 0;
   if (op->cg_variant == BP_CG_SINGLE_REDUCTION) {
-    rc = pcg_run_sr(op, which, b, x, op->dinv[dinv_slot(which)], rtol, maxit, fixed_iters != 0,
+    rc = pcg_run_sr(op, which, b, x, op->dinv[dinv_slot(op, which)], rtol, maxit, fixed_iters != 0,
                     false, s, &iters, &ms, &apply_ms, &apply_count);
   } else {
-    rc = pcg_run<double>(op, which, false, b, x, op->dinv[dinv_slot(which)], op->r, op->pv,
+    rc = pcg_run<double>(op, which, false, b, x, op->dinv[dinv_slot(op, which)], op->r, op->pv,
                          op->w, rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
                          &apply_count);
   }

@@ -72,6 +72,18 @@ def test_zero_beta_is_stiffness_and_beta_can_be_reset():
         assert rel(host(c.op.apply(HELM, u)), a) > 1e-3
         c.op.set_helmholtz(0.0)
         assert rel(host(c.op.apply(HELM, u)), a) <= 1e-15
+        # solves: without a beta term H uses the stiffness's inverse diagonal;
+        # with one, its own (allocated when beta is set, computed at the first solve)
+        b = u * torch.from_numpy(1.0 - c.mesh.boundary).cuda()
+        xa, _ = c.op.pcg_solve(b, which=STIFF, maxit=4, fixed_iters=True)
+        xh, _ = c.op.pcg_solve(b, which=HELM, maxit=4, fixed_iters=True)
+        assert rel(host(xh), host(xa)) <= 1e-13
+        c.op.set_helmholtz(2.0)
+        xb, _ = c.op.pcg_solve(b, which=HELM, maxit=4, fixed_iters=True)
+        assert rel(host(xb), host(xa)) > 1e-3
+        c.op.set_helmholtz(0.0)
+        xh, _ = c.op.pcg_solve(b, which=HELM, maxit=4, fixed_iters=True)
+        assert rel(host(xh), host(xa)) <= 1e-13
     finally:
         c.close()
 
