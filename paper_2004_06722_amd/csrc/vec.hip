@@ -404,7 +404,8 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_xp(int64_t n, T 
   const int comp = blockIdx.y;
   const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
-  const bool dir = !sc->done;
+  // z is loaded whether or not the direction is updated, so that its load
+  // does not wait for the done flag; only the store of p depends on it
   T pv[K], xv[K], zv[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -413,9 +414,10 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_xp(int64_t n, T 
     if (v < n) {
       pv[j] = ld_v<NT>(p + comp * n + v);
       xv[j] = ld_v<NT>(x + comp * n + v);
-      if (dir) zv[j] = ld_v<NT>(z + comp * n + v);
+      zv[j] = ld_v<NT>(z + comp * n + v);
     }
   }
+  const bool dir = !sc->done;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int64_t v = v0 + j * TH;
