@@ -302,7 +302,7 @@ int pcg_run_sr(bp_op op, int which, const double *b, double *x, const double *di
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
     for (int c = 0; c < chunk; ++c) {
-      sr_update<double>(nc, n, x, u, w, p, sv, dinv, pv, op->sc, s);
+      sr_update<double>(nc, n, x, u, w, p, sv, dinv, pv, op->sc, s, check);
       // the operator and finisher of the last fixed iteration would only
       // prepare a step that is not taken
       if (fixed && it + c == maxit - 1) break;

@@ -99,7 +99,7 @@ void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const
              double *part, hipStream_t s);
 template <typename T>
 void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
-               DevScalars *sc, hipStream_t s);
+               DevScalars *sc, hipStream_t s, bool check = true);
 void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba,
             DevScalars *sc, hipStream_t s);
 

@@ -562,9 +562,9 @@ template <typename T, bool NT>
 __global__ __launch_bounds__(kGroupThreads<T>) void k_sr_update(
     int64_t n, T *__restrict__ x, T *__restrict__ u, T *__restrict__ w, T *__restrict__ p,
     T *__restrict__ sv, const T *__restrict__ dinv, double *__restrict__ part,
-    const DevScalars *__restrict__ sc) {
+    const DevScalars *__restrict__ sc, int check) {
   constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
-  if (sc->done) return;
+  if (check && sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
@@ -908,13 +908,15 @@ void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const
 
 template <typename T>
 void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
-               DevScalars *sc, hipStream_t s) {
+               DevScalars *sc, hipStream_t s, bool check) {
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
     hipLaunchKernelGGL((k_sr_update<T, true>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc);
+                       dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc,
+                       check ? 1 : 0);
   else
     hipLaunchKernelGGL((k_sr_update<T, false>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc);
+                       dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc,
+                       check ? 1 : 0);
 }
 
 template <int NC>
@@ -949,7 +951,7 @@ void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba
 template void sr_init<double>(int, int64_t, const double *, double *, double *, double *,
                               double *, double *, const double *, double *, hipStream_t);
 template void sr_update<double>(int, int64_t, double *, double *, double *, double *, double *,
-                                const double *, double *, DevScalars *, hipStream_t);
+                                const double *, double *, DevScalars *, hipStream_t, bool);
 
 template <typename T>
 void cg_restart(int nc, int64_t n, T *r, T *p, const T *dinv, double *part,
