@@ -426,3 +426,28 @@ def test_errors_are_reported():
             op.apply(STIFF, dev(np.zeros(m.nglobal, np.float32)))
     finally:
         op.close()
+
+
+@pytest.mark.parametrize("sr", [False, True])
+def test_operator_timing_option(sr):
+    # BP_OPT_TIME_APPLY: one event pair per operator launch of the loop (the
+    # operator of the initial residual is outside it), summed into apply_ms;
+    # the iterates are those of the untimed solve
+    from paper_2004_06722_amd._lib import BP_OPT_TIME_APPLY
+    c = Case(5, 3, 3, 3, 3, seed=41)
+    try:
+        c.op.set_cg_variant(sr)
+        b = dev(c.vec(42) * (1 - c.mesh.boundary))
+        x0, st0 = c.op.pcg_solve(b, maxit=6, fixed_iters=True)
+        assert st0["apply_count"] == 0 and st0["apply_ms"] == 0.0
+        c.op.set_option(BP_OPT_TIME_APPLY, 1)
+        x1, st1 = c.op.pcg_solve(b, maxit=6, fixed_iters=True)
+        # the single-reduction form skips the operator of the last fixed iteration
+        assert st1["apply_count"] == (5 if sr else 6)
+        assert 0.0 < st1["apply_ms"] < st1["ms"]
+        assert rel(host(x1), host(x0)) <= 1e-14
+        c.op.set_option(BP_OPT_TIME_APPLY, 0)
+        _, st2 = c.op.pcg_solve(b, maxit=6, fixed_iters=True)
+        assert st2["apply_count"] == 0
+    finally:
+        c.close()
