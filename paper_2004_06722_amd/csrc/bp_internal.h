@@ -84,6 +84,7 @@ struct bp_op_s {
   bp::DevScalars *sc = nullptr;   // device
   bp::DevScalars *sc_host = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evm0 = nullptr, evm1 = nullptr;  // around a mixed solve (BP_SETUP_FP32)
   bool time_apply = false;
   int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
   int cg_variant = 0;  // BP_CG_STANDARD or BP_CG_SINGLE_REDUCTION (bp_pcg_solve)

@@ -79,6 +79,8 @@ void release(bp_op op) {
   if (op->sc_host) (void)hipHostFree(op->sc_host);
   if (op->ev0) (void)hipEventDestroy(op->ev0);
   if (op->ev1) (void)hipEventDestroy(op->ev1);
+  if (op->evm0) (void)hipEventDestroy(op->evm0);
+  if (op->evm1) (void)hipEventDestroy(op->evm1);
   for (auto ev : op->apply_ev)
     if (ev) (void)hipEventDestroy(ev);
   delete op;
@@ -262,7 +264,7 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
     if (apply_count_out) *apply_count_out = timed;
   }
   if (op->sc_host->nonfinite) return set_error(BP_ERR_NONFINITE, "non-finite value in CG reductions");
-  if (op->sc_host->breakdown) return set_error(BP_ERR_BREAKDOWN, "CG breakdown: p.Ap < 0");
+  if (op->sc_host->breakdown) return set_error(BP_ERR_BREAKDOWN, "CG breakdown: p.Ap <= 0 along a non-zero direction");
   return BP_OK;
 }
 
@@ -381,11 +383,13 @@ int mixed_reliable(bp_op op, const double *b, double *x, double rtol, double del
   double worst = 0.0;
   int rc = true_residual(op, b, x, &worst, s);
   if (rc == BP_OK && worst > rtol && max_updates > 0) {
-    to_f32(op->r, op->r32, nv, s);
+    // the first FP32 right-hand side is the FP64 residual (b and r of the
+    // FP32 iteration are distinct buffers)
+    to_f32(op->r, op->b32, nv, s);
     fill_f32(op->x32, nv, 0.0f, s);
     bool resume = false;
     for (;;) {
-      rc = pcg_run<float>(op, BP_STIFF, true, op->r32, op->x32, op->dinv32, op->r32, op->p32,
+      rc = pcg_run<float>(op, BP_STIFF, true, op->b32, op->x32, op->dinv32, op->r32, op->p32,
                           op->w32, delta, max_iters - iters, false, true, s, &iters, nullptr,
                           nullptr, nullptr, resume);
       if (rc) break;
@@ -600,6 +604,8 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
     TRY(dmalloc(&op->b32, nv));
     TRY(dmalloc(&op->dinv32, nglobal));
     if (op->tr_off) TRY(dmalloc(&op->wl32, nl * ncomp));
+    TRYHIP(hipEventCreate(&op->evm0));
+    TRYHIP(hipEventCreate(&op->evm1));
   }
 #undef TRY
 #undef TRYHIP
@@ -765,9 +771,8 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
   const int nc = op->ncomp;
   const int64_t n = op->nglobal, nv = n * nc;
   const bool masked = op->has_dirichlet;
-  hipEvent_t t0, t1;
-  BP_HIP(hipEventCreate(&t0));
-  BP_HIP(hipEventCreate(&t1));
+  // the events were created by bp_setup: the solve allocates nothing
+  hipEvent_t t0 = op->evm0, t1 = op->evm1;
   BP_HIP(hipEventRecord(t0, s));
   int outer = 0, inner_total = 0;
   if (op->mixed_mode == BP_MIXED_RELIABLE) {
@@ -807,8 +812,6 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
   BP_HIP(hipEventSynchronize(t1));
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, t0, t1);
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->iters = inner_total;

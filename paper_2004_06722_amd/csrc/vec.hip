@@ -122,6 +122,12 @@ __device__ __forceinline__ bool converged(const DevScalars *sc, int nc) {
   return ok;
 }
 
+// CG breakdown test: a step length alpha = num / den that is not positive
+// (or not defined) while num = (r, z) is non-zero
+__device__ __forceinline__ bool indefinite(double num, double den) {
+  return num != 0.0 && (den == 0.0 || (num > 0.0) != (den > 0.0));
+}
+
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
   for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
@@ -227,14 +233,28 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
   }
   __shared__ double res[NC];
   reduce_columns<NC>(part, nb, res);
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
+    int stop = 0;
     for (int c = 0; c < nc; ++c) {
       const double pap = res[c];
       sc->pap[c] = pap;
       sc->alpha[c] = pap != 0.0 ? sc->rz[c] / pap : 0.0;
-      if (pap < 0.0) sc->breakdown = 1;
-      if (!isfinite(pap)) sc->nonfinite = 1;
+      // alpha = (r.z) / (p.Ap) must be positive when r.z != 0: zero curvature
+      // or curvature of the other sign than r.z means the preconditioned
+      // operator is not definite on this Krylov space
+      if (indefinite(sc->rz[c], pap)) {
+        sc->breakdown = 1;
+        stop = 1;
+      }
+      if (!isfinite(pap)) {
+        sc->nonfinite = 1;
+        stop = 1;
+      }
     }
+    // with a stopping test, end the solve here: the residual and solution
+    // updates of this iteration are skipped, x keeps the last iterate
+    if (check && stop) sc->done = sc->halted = 1;
+  }
 }
 
 // z -= alpha dinv w (r -= alpha w on the stored z = dinv r); w = 0;
@@ -621,19 +641,20 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_sr(const double *__restrict
   reduce_columns<WV>(pv, nbv, rv);
   reduce_columns<NC>(pa, nba, ra);
   if (threadIdx.x == 0) {
-    int bad = 0;
+    int bad = 0, brk = 0;
     for (int c = 0; c < NC; ++c) {
       const double g = rv[c], delta = ra[c];
       double alpha, beta = 0.0;
+      // (r, u) != 0 with a curvature that does not give alpha > 0 is a breakdown
       if (FIRST) {
         alpha = delta != 0.0 ? g / delta : 0.0;
         sc->bb[c] = rv[2 * NC + c];
-        if (delta < 0.0) sc->breakdown = 1;
+        if (indefinite(g, delta)) brk = 1;
       } else {
         beta = sc->rz[c] != 0.0 ? g / sc->rz[c] : 0.0;
         const double den = delta - (sc->alpha[c] != 0.0 ? beta * g / sc->alpha[c] : 0.0);
         alpha = den != 0.0 ? g / den : 0.0;
-        if (den < 0.0) sc->breakdown = 1;
+        if (indefinite(g, den)) brk = 1;
       }
       sc->rz[c] = g;
       sc->pap[c] = delta;
@@ -644,13 +665,16 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_sr(const double *__restrict
     }
     if (FIRST) {
       sc->iters = 0;
-      sc->breakdown = sc->breakdown && !bad;
+      sc->breakdown = brk && !bad;
       sc->halted = 0;
     } else {
       sc->iters += 1;
+      sc->breakdown = sc->breakdown || brk;
     }
     sc->nonfinite = bad;
-    sc->done = bad || (!sc->fixed && converged(sc, NC));
+    // a breakdown ends a solve that has a stopping test before the step
+    // that would use its alpha (fixed iteration counts keep going)
+    sc->done = bad || (!sc->fixed && (brk || converged(sc, NC)));
   }
 }
 

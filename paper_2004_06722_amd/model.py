@@ -20,6 +20,12 @@ VECTOR_WORDS_OPERATOR = 2
 VECTOR_WORDS_CG = 10
 
 
+def points(p: int, E: int) -> int:
+    """n = p^3 E, the point count of section 2 (no boundary or redundancy
+    effects): the n of every DOFs/s figure."""
+    return p ** 3 * E
+
+
 def quadrature(bp: int, p: int) -> int:
     return p + 1 if bp in (5, 6) else p + 2
 

@@ -14,13 +14,17 @@ Conventions (paper section 4, eq. (xijk)/(uijk)): a node of element e is
 (i, j, k) with i the fastest index, local id l = i + p1*(j + p1*k); elements
 are numbered lexicographically (x fastest); global nodes are numbered
 lexicographically on the (p*Ex+1) x (p*Ey+1) x (p*Ez+1) lattice.
+scramble_mesh turns such a mesh into one with an arbitrary map: random global
+ids, element order and element orientations (the 24 proper cube symmetries).
 """
 from .mesh import (element_grid, BrickMesh, brick_mesh, element_coordinates,
-                   vertex_perturbation, trilinear_nodes)
+                   vertex_perturbation, trilinear_nodes, cube_rotations,
+                   rotated_local_ids, scramble_mesh)
 from .fields import (rhs_uniform, manufactured_u, manufactured_f, kappa_log,
                      fd_direction)
 
 __all__ = ["element_grid", "BrickMesh", "brick_mesh", "element_coordinates",
            "vertex_perturbation",
-           "trilinear_nodes", "rhs_uniform", "manufactured_u", "manufactured_f",
+           "trilinear_nodes", "cube_rotations", "rotated_local_ids", "scramble_mesh",
+           "rhs_uniform", "manufactured_u", "manufactured_f",
            "kappa_log", "fd_direction"]

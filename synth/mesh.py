@@ -167,3 +167,64 @@ def brick_mesh(ex: int, ey: int, ez: int, p: int, ref_nodes: np.ndarray,
     boundary = ((gi == 0) | (gi == nx - 1) | (gj == 0) | (gj == ny - 1)
                 | (gk == 0) | (gk == nz - 1)).astype(np.uint8)
     return BrickMesh(ex, ey, ez, p, elem_dofs, node_xyz, boundary, nglobal)
+
+
+def cube_rotations() -> list[tuple[tuple[int, int, int], tuple[int, int, int]]]:
+    """The 24 proper symmetries of the reference cube [-1,1]^3.
+
+    Each is (perm, sign): new reference coordinate d is sign[d] times old
+    coordinate perm[d]. The signed permutation matrix has determinant +1, so
+    composing an element's map with it keeps the Jacobian positive.
+    """
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        inv = sum(1 for a in range(3) for b in range(a + 1, 3) if perm[a] > perm[b])
+        for sign in itertools.product((1, -1), repeat=3):
+            if (-1) ** inv * sign[0] * sign[1] * sign[2] == 1:
+                out.append((perm, sign))
+    return out
+
+
+def rotated_local_ids(p1: int, perm, sign) -> np.ndarray:
+    """old[l'] = the old local id of new local node l' under a cube rotation.
+
+    New node (i'_0, i'_1, i'_2) sits where old index i_d = i'_perm[d] if
+    sign[d] > 0 and p - i'_perm[d] otherwise (the node lattice is symmetric
+    about the cube's centre, so a rotation maps nodes onto nodes).
+    """
+    l = np.arange(p1 ** 3, dtype=np.int64)
+    new = np.stack([l % p1, (l // p1) % p1, l // (p1 * p1)])     # new[d] = i'_d
+    old = np.empty_like(new)
+    for d in range(3):
+        src = new[perm[d]]
+        old[d] = src if sign[d] > 0 else (p1 - 1) - src
+    return old[0] + p1 * (old[1] + p1 * old[2])
+
+
+def scramble_mesh(mesh: BrickMesh, seed: int) -> BrickMesh:
+    """The same mesh with an arbitrary gather map (input data only).
+
+    Global ids are renumbered by a seeded random permutation, the elements
+    are listed in a random order, and the local axes of every element are
+    turned by a random proper cube symmetry (its node list re-indexed, its
+    geometry unchanged). The discrete operator is then P A P^T for the
+    renumbering P: nothing of the tensor-grid numbering is left for a solver
+    to rely on.
+    """
+    rng = np.random.default_rng(seed)
+    p1 = mesh.p1
+    E = mesh.elem_dofs.shape[0]
+    newid = rng.permutation(mesh.nglobal).astype(np.int64)      # old id -> new id
+    order = rng.permutation(E)                                   # new element -> old
+    rots = cube_rotations()
+    tables = np.stack([rotated_local_ids(p1, *r) for r in rots])  # [24, p1^3]
+    which = rng.integers(0, len(rots), size=E)
+    loc = tables[which]                                          # [E, p1^3] old local id
+    src = order[:, None]
+    elem_dofs = newid[mesh.elem_dofs[src, loc]]
+    node_xyz = mesh.node_xyz[src, loc]
+    boundary = np.empty_like(mesh.boundary)
+    boundary[newid] = mesh.boundary
+    return BrickMesh(mesh.ex, mesh.ey, mesh.ez, mesh.p, elem_dofs, node_xyz, boundary,
+                     mesh.nglobal)

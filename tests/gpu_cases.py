@@ -19,7 +19,8 @@ def rel(a, b):
 class Case:
     """Oracle Discretization + library Operator on one seeded mesh."""
 
-    def __init__(self, bp, p, ex, ey, ez, seed=0, ncomp=1, fp32=False, dirichlet=None):
+    def __init__(self, bp, p, ex, ey, ez, seed=0, ncomp=1, fp32=False, dirichlet=None,
+                 scramble=None):
         import paper_2004_06722_amd.bp as B
         self.bp, self.p, self.ncomp = bp, p, ncomp
         q, quad = B.bp_quadrature(bp, p)
@@ -29,12 +30,17 @@ class Case:
         # oracle side
         orule = oracle_rule(bp, p)
         om = synth.brick_mesh(ex, ey, ez, p, orule.xi, seed)
+        if scramble is not None:
+            # arbitrary map: random ids, element order and orientations
+            om = synth.scramble_mesh(om, scramble)
         self.mesh = om
         self.dir = om.boundary if dirichlet else None
         self.disc = Discretization(orule, om.elem_dofs, om.node_xyz, om.nglobal, self.dir)
         # library side: nodes at the library's own GLL points
         xi, _ = B.rule(p + 1, B.GLL)
         lm = synth.brick_mesh(ex, ey, ez, p, xi, seed)
+        if scramble is not None:
+            lm = synth.scramble_mesh(lm, scramble)
         assert np.array_equal(lm.elem_dofs, om.elem_dofs)
         self.op = B.Operator(p, q, quad, lm.elem_dofs, lm.node_xyz, lm.nglobal,
                              self.dir, ncomp=ncomp, fp32=fp32)

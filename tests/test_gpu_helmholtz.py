@@ -121,3 +121,53 @@ def test_helmholtz_without_dirichlet_converges():
         assert rel(host(x), ref) <= 1e-11
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("sr", [False, True])
+def test_indefinite_operator_reports_breakdown(sr):
+    # H = A + beta B with beta = -300 is indefinite on this mesh (the smooth
+    # modes have generalised eigenvalues near 3 pi^2 < 300) while diag(H)
+    # stays positive, and for the smooth rhs M f the first step has r.z > 0
+    # and p.Hp < 0 (checked on the oracle below). A tolerance solve stops
+    # there, not at maxit, with BP_ERR_BREAKDOWN and x = x0 = 0; the
+    # fixed-count mode runs every iteration and reports the breakdown at the
+    # end.
+    import ctypes
+
+    import synth
+    from oracle.operators import MASS
+    from paper_2004_06722_amd import _lib
+    c = Case(5, 3, 3, 3, 3, seed=66)
+    try:
+        beta = -300.0
+        hd = helm_disc(c, beta)
+        f = synth.manufactured_f(c.mesh.global_coords())
+        bh = c.disc.apply(MASS, f, masked=False) * c.disc.mask
+        z = hd.jacobi_inverse(HELM) * bh
+        assert hd.diag(HELM)[c.mesh.boundary == 0].min() > 0
+        assert bh @ z > 0 and z @ hd.apply(HELM, z) < 0
+        c.op.set_cg_variant(sr)
+        c.op.set_helmholtz(beta)
+        b = dev(bh)
+        x = torch.zeros_like(b)
+        lib = _lib.load()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for fixed, maxit in ((0, 50), (1, 6)):
+            x.zero_()
+            st = _lib.PcgStats()
+            rc = lib.bp_pcg_solve(c.op._h, HELM, ctypes.c_void_p(b.data_ptr()),
+                                  ctypes.c_void_p(x.data_ptr()), 1e-8, maxit, fixed,
+                                  ctypes.byref(st), stream)
+            torch.cuda.synchronize()
+            assert rc == _lib.BP_ERR_BREAKDOWN, (fixed, rc)
+            if not fixed:
+                assert st.iters == 0, st.iters
+                assert float(torch.abs(x).max()) == 0.0
+            else:
+                assert st.iters == maxit
+        # the operator stays usable: with beta > 0 the solve converges
+        c.op.set_helmholtz(2.0)
+        xs, st = c.op.pcg_solve(b, which=HELM, rtol=1e-10, maxit=500)
+        assert st["converged"]
+    finally:
+        c.close()

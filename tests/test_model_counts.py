@@ -37,3 +37,27 @@ def test_mass_flops_reduce_to_the_tensor_form(p):
     p1, q = p + 1, p + 2
     chain = 2 * 2 * (q * p1 ** 3 + q * q * p1 ** 2 + q ** 3 * p1)
     assert model.apply_flops_per_element(1, p) == pytest.approx(chain + q ** 3)
+
+
+def _paper_counts():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_counts.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_point_count_matches_the_paper_example():
+    # section 2: p = 7 with E = 2^14 and 2^16 gives the printed n
+    for row in _paper_counts()["n_points"]:
+        assert model.points(row["p"], row["E"]) == row["n"]
+
+
+@pytest.mark.parametrize("row", _paper_counts()["interpolate_first"])
+def test_interpolate_first_relative_work_matches_the_paper(row):
+    # section 5 after eq. (work3): interpolating to the quadrature points first
+    # changes the work of eq. (work2) by about -25% at gamma = 1 and +12% at
+    # gamma = 3/2 (leading order: large p1, where the p1^3 term is small)
+    p1, g = row["p1_large"], row["gamma"]
+    change = model.work_interpolate_first(p1, g) / model.work_direct(p1, g) - 1.0
+    assert abs(change - row["relative_change"]) <= row["tolerance"], change
