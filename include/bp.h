@@ -42,7 +42,7 @@ enum bp_status {
   BP_ERR_MESH = -2,       /* bad mesh: Jacobian <= 0, index out of range    */
   BP_ERR_HIP = -3,        /* a HIP runtime call failed                       */
   BP_ERR_NONFINITE = -4,  /* NaN or Inf in an input or a reduction           */
-  BP_ERR_BREAKDOWN = -5,  /* CG breakdown: p.Ap <= 0 with p != 0             */
+  BP_ERR_BREAKDOWN = -5,  /* CG breakdown: r.z != 0 and (r.z)/(p.Ap) not > 0  */
   BP_ERR_OOM = -6         /* device or host allocation failed                */
 };
 
@@ -193,10 +193,41 @@ typedef struct {
  *   st: may be NULL. Components use independent CG scalars. Entries of b on
  *   Dirichlet nodes are ignored (read as 0).
  * The call synchronises the stream before it returns.
- * Errors: BP_ERR_NONFINITE if b holds NaN/Inf, BP_ERR_BREAKDOWN if p.Ap < 0.
+ * Errors: BP_ERR_NONFINITE if b holds NaN/Inf; BP_ERR_BREAKDOWN when a step
+ * length alpha = (r.z) / (p.Ap) is not positive while r.z != 0 (an operator
+ * or preconditioner that is not definite on the Krylov space). With a
+ * stopping test the solve ends at that iteration and x keeps the last
+ * iterate (stats give the iterations completed); in fixed-iteration mode all
+ * maxit iterations run and the error is returned at the end.
  */
 int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol,
                  int maxit, int fixed_iters, bp_pcg_stats *st, void *stream);
+
+/*
+ * bp_pcg_solve_static -- bp_pcg_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, results and errors
+ * as bp_pcg_solve with the standard recurrences (BP_OPT_CG_VARIANT is not
+ * consulted), but the iteration's workspace -- the vectors z = D^-1 r, p and
+ * w = A p, the partial-sum tables and the device scalars -- lives in one
+ * static device array of BP_STATIC_WS_MB MiB per device (resolved by
+ * bp_setup), not in the operator's buffers. Nothing is allocated or freed.
+ * Limits and sharing:
+ *   - the operator must fit: 3 nglobal ncomp doubles plus the partial sums
+ *     (nglobal ncomp up to about 2.7e6); larger operators return BP_ERR_ARG
+ *     with the bytes needed (use bp_pcg_solve);
+ *   - every call on a device shares that device's array and leaves its last
+ *     contents there; each call writes what it reads (w is cleared, the
+ *     scalars uploaded) before using it, but calls that overlap on one
+ *     device (different streams or threads) race and must be serialised by
+ *     the caller;
+ *   - the Jacobi diagonal and, for Gauss-Legendre mass operators, the
+ *     element-local output buffer are the operator's own (set up by
+ *     bp_setup), as in bp_pcg_solve.
+ */
+#define BP_STATIC_WS_MB 64
+int bp_pcg_solve_static(bp_op op, int which, const double *b, double *x, double rtol,
+                        int maxit, int fixed_iters, bp_pcg_stats *st, void *stream);
 
 /*
  * bp_pcg_solve_mixed -- FP64 defect correction around an FP32 Jacobi-PCG

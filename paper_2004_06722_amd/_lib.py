@@ -19,6 +19,7 @@ BP_OPT_MIXED_MODE = 2
 BP_MIXED_RESTART, BP_MIXED_RELIABLE = 0, 1
 BP_OPT_CG_VARIANT = 3
 BP_CG_STANDARD, BP_CG_SINGLE_REDUCTION = 0, 1
+BP_STATIC_WS_MB = 64
 
 ERROR_NAMES = {BP_ERR_ARG: "BP_ERR_ARG", BP_ERR_MESH: "BP_ERR_MESH", BP_ERR_HIP: "BP_ERR_HIP",
                BP_ERR_NONFINITE: "BP_ERR_NONFINITE", BP_ERR_BREAKDOWN: "BP_ERR_BREAKDOWN",
@@ -56,6 +57,7 @@ SIGNATURES = {
     "bp_apply_local": (_i, [_vp, _i, _i, _vp, _vp, _vp]),
     "bp_diag": (_i, [_vp, _i, _vp, _u, _vp]),
     "bp_pcg_solve": (_i, [_vp, _i, _vp, _vp, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),
+    "bp_pcg_solve_static": (_i, [_vp, _i, _vp, _vp, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),
     "bp_pcg_solve_mixed": (_i, [_vp, _vp, _vp, _d, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),
     "bp_grad_kappa": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "bp_set_option": (_i, [_vp, _i, _i]),

@@ -8,12 +8,25 @@
 #include <climits>
 #include <vector>
 
+#include <mutex>
+
 #include "bp_internal.h"
 #include "launch.h"
 
 namespace bp {
 
 static thread_local std::string g_last_error;
+
+// Workspace of bp_pcg_solve_static: a file-scope device array (one copy on
+// every device the library runs on, held until the process ends). Host code
+// never uses its name as an address: bp_setup resolves the device address
+// once per device (hipGetSymbolAddress, with that device current) and the
+// solve passes that address to the kernels.
+constexpr size_t kStaticWsBytes = size_t(BP_STATIC_WS_MB) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void *g_scratch_ptr[kMaxDevices] = {};
 
 int set_error(int code, const std::string &msg) {
   g_last_error = msg;
@@ -164,37 +177,96 @@ int ensure_dinv(bp_op op, int which, hipStream_t s) {
   return BP_OK;
 }
 
-int upload_scalars(bp_op op, double rtol, bool fixed, hipStream_t s) {
-  std::memset(op->sc_host, 0, sizeof(DevScalars));
-  op->sc_host->tol2 = rtol * rtol;
-  op->sc_host->fixed = fixed ? 1 : 0;
-  BP_HIP(hipMemcpyAsync(op->sc, op->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+// Partial-sum table and device scalars of one CG run: the operator's own
+// (op->part, op->sc) or those in the static workspace of bp_pcg_solve_static.
+struct CgWork {
+  double *part;
+  DevScalars *sc;
+};
+
+CgWork own_work(bp_op op) { return CgWork{op->part, op->sc}; }
+
+// Device address of `scratch` on device dev (current), looked up once.
+int resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(BP_ERR_ARG, "device index " + std::to_string(dev) + " beyond the static table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev]) return BP_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return set_error(BP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
   return BP_OK;
 }
 
-int download_scalars(bp_op op, hipStream_t s) {
-  BP_HIP(hipMemcpyAsync(op->sc_host, op->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+// Layout of the static workspace for an operator: device scalars, the
+// partial-sum table (as op->part), then z, p, w ([ncomp][nglobal] each),
+// every block 256-byte aligned. Returns the bytes needed.
+size_t scratch_layout(const bp_op_s *op, unsigned char *base, CgWork *ws, double **z, double **p,
+                      double **w) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t nv = (size_t)op->nglobal * op->ncomp;
+  size_t off = 0;
+  const size_t o_sc = off;
+  off += up(sizeof(DevScalars));
+  const size_t o_part = off;
+  off += up((size_t)op->part_len * sizeof(double));
+  size_t o_vec[3];
+  for (int k = 0; k < 3; ++k) {
+    o_vec[k] = off;
+    off += up(nv * sizeof(double));
+  }
+  if (base) {
+    ws->sc = reinterpret_cast<DevScalars *>(base + o_sc);
+    ws->part = reinterpret_cast<double *>(base + o_part);
+    *z = reinterpret_cast<double *>(base + o_vec[0]);
+    *p = reinterpret_cast<double *>(base + o_vec[1]);
+    *w = reinterpret_cast<double *>(base + o_vec[2]);
+  }
+  return off;
+}
+
+int upload_scalars(bp_op op, DevScalars *sc, double rtol, bool fixed, hipStream_t s) {
+  std::memset(op->sc_host, 0, sizeof(DevScalars));
+  op->sc_host->tol2 = rtol * rtol;
+  op->sc_host->fixed = fixed ? 1 : 0;
+  BP_HIP(hipMemcpyAsync(sc, op->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+  return BP_OK;
+}
+
+int download_scalars(bp_op op, const DevScalars *sc, hipStream_t s) {
+  BP_HIP(hipMemcpyAsync(op->sc_host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
   BP_HIP(hipStreamSynchronize(s));
   return BP_OK;
 }
+int upload_scalars(bp_op op, double rtol, bool fixed, hipStream_t s) {
+  return upload_scalars(op, op->sc, rtol, fixed, s);
+}
+int download_scalars(bp_op op, hipStream_t s) { return download_scalars(op, op->sc, s); }
 
 // Jacobi-PCG on precision T. x0_zero: x is zero on entry (skips A x0).
 // The buffer `r` holds the preconditioned residual z = dinv r during the
 // iteration (ten vector words per DOF and iteration; see k_cg_init).
 // resume: continue from the device scalars and the z, p, w (w zero) that a
 // previous call or cg_restart left, without the set-up (b, rtol unused).
+// ws: partial sums and device scalars of the run (own_work(op) unless the
+// caller brings its own).
 template <typename T>
-int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r, T *p, T *w,
-            double rtol, int maxit, bool fixed, bool x0_zero, hipStream_t s, int *iters_out,
-            float *ms_out, double *apply_ms_out = nullptr, int *apply_count_out = nullptr,
-            bool resume = false) {
+int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, const T *dinv,
+            T *r, T *p, T *w, double rtol, int maxit, bool fixed, bool x0_zero, hipStream_t s,
+            int *iters_out, float *ms_out, double *apply_ms_out = nullptr,
+            int *apply_count_out = nullptr, bool resume = false) {
   const int nc = op->ncomp;
   const int64_t n = op->nglobal, nv = n * nc;
   const bool masked = op->has_dirichlet;
   const int64_t nb_apply = apply_rows(op, which), nb_vec = vec_blocks(n);
+  double *const part = ws.part;
+  DevScalars *const sc = ws.sc;
   int rc = BP_OK;
   if (!resume) {
-    rc = upload_scalars(op, rtol, fixed, s);
+    rc = upload_scalars(op, sc, rtol, fixed, s);
     if (rc) return rc;
     if constexpr (sizeof(T) == 8)
       fill_f64((double *)w, nv, 0.0, s);
@@ -204,7 +276,7 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
       rc = launch_apply(op, which, f32, x, w, masked, nullptr, nullptr, s);
       if (rc) return rc;
     }
-    cg_init<T>(nc, n, b, r, w, p, dinv, op->part, op->sc, s);
+    cg_init<T>(nc, n, b, r, w, p, dinv, part, sc, s);
     BP_HIP(hipGetLastError());
   }
   BP_HIP(hipEventRecord(op->ev0, s));
@@ -213,7 +285,7 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
   // a fixed number of iterations has no stopping test to honour: the kernels
   // then skip the done flag (nothing waits on loading it)
   const bool check = !fixed;
-  const int *done = check ? &op->sc->done : nullptr;
+  const int *done = check ? &sc->done : nullptr;
   // mass on Gauss-Legendre points: the kernel stores w_L and the residual
   // update gathers w = Q^T w_L itself (w stays zero)
   const bool mass_wl = which == BP_MASS && op->tr_off != nullptr;
@@ -225,29 +297,29 @@ int pcg_run(bp_op op, int which, bool f32, const T *b, T *x, const T *dinv, T *r
     for (int c = 0; c < chunk; ++c) {
       const bool tm = op->time_apply && timed < kMaxTimedApplies;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
-      rc = mass_wl ? launch_mass_wl(op, f32, p, masked, op->part, done, s)
-                   : launch_apply(op, which, f32, p, w, masked, op->part, done, s);
+      rc = mass_wl ? launch_mass_wl(op, f32, p, masked, part, done, s)
+                   : launch_apply(op, which, f32, p, w, masked, part, done, s);
       if (rc) return rc;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
-      cg_fin_alpha(nc, op->part, nb_apply, op->sc, s, check);
+      cg_fin_alpha(nc, part, nb_apply, sc, s, check);
       if (mass_wl)
-        cg_update_r_gather<T>(nc, n, nl, r, wl, op->tr_off, op->tr_pos, dinv, op->part, op->sc,
-                              s, check);
+        cg_update_r_gather<T>(nc, n, nl, r, wl, op->tr_off, op->tr_pos, dinv, part, sc, s,
+                              check);
       else
-        cg_update_r<T>(nc, n, r, w, dinv, op->part, op->sc, s, check);
-      cg_fin_beta(nc, nb_vec, op->part, op->sc, s, check);
-      cg_update_xp<T>(nc, n, x, p, r, op->sc, s, check);
+        cg_update_r<T>(nc, n, r, w, dinv, part, sc, s, check);
+      cg_fin_beta(nc, nb_vec, part, sc, s, check);
+      cg_update_xp<T>(nc, n, x, p, r, sc, s, check);
     }
     BP_HIP(hipGetLastError());
     it += chunk;
     if (!fixed) {
-      rc = download_scalars(op, s);
+      rc = download_scalars(op, sc, s);
       if (rc) return rc;
       if (op->sc_host->done) break;
     }
   }
   BP_HIP(hipEventRecord(op->ev1, s));
-  rc = download_scalars(op, s);
+  rc = download_scalars(op, sc, s);
   if (rc) return rc;
   float ms = 0.0f;
   BP_HIP(hipEventElapsedTime(&ms, op->ev0, op->ev1));
@@ -389,9 +461,9 @@ int mixed_reliable(bp_op op, const double *b, double *x, double rtol, double del
     fill_f32(op->x32, nv, 0.0f, s);
     bool resume = false;
     for (;;) {
-      rc = pcg_run<float>(op, BP_STIFF, true, op->b32, op->x32, op->dinv32, op->r32, op->p32,
-                          op->w32, delta, max_iters - iters, false, true, s, &iters, nullptr,
-                          nullptr, nullptr, resume);
+      rc = pcg_run<float>(op, own_work(op), BP_STIFF, true, op->b32, op->x32, op->dinv32,
+                          op->r32, op->p32, op->w32, delta, max_iters - iters, false, true, s,
+                          &iters, nullptr, nullptr, nullptr, resume);
       if (rc) break;
       const bool reached = op->sc_host->done != 0;
       dc_accumulate(nv, x, op->x32, s);
@@ -502,7 +574,11 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
     return set_error(BP_ERR_HIP, "bp_setup: no HIP device");
   }
 
-  int rc = BP_OK;
+  int rc = resolve_scratch(op->device);
+  if (rc) {
+    release(op);
+    return rc;
+  }
 #define TRY(x)          \
   do {                  \
     rc = (x);           \
@@ -741,10 +817,54 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
     rc = pcg_run_sr(op, which, b, x, op->dinv[dinv_slot(op, which)], rtol, maxit, fixed_iters != 0,
                     false, s, &iters, &ms, &apply_ms, &apply_count);
   } else {
-    rc = pcg_run<double>(op, which, false, b, x, op->dinv[dinv_slot(op, which)], op->r, op->pv,
-                         op->w, rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
-                         &apply_count);
+    rc = pcg_run<double>(op, own_work(op), which, false, b, x, op->dinv[dinv_slot(op, which)],
+                         op->r, op->pv, op->w, rtol, maxit, fixed_iters != 0, false, s, &iters,
+                         &ms, &apply_ms, &apply_count);
   }
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->iters = iters;
+    st->ms = ms;
+    st->apply_ms = apply_ms;
+    st->apply_count = apply_count;
+    fill_stats(op, rtol, st);
+  }
+  return rc;
+}
+
+int bp_pcg_solve_static(bp_op op, int which, const double *b, double *x, double rtol,
+                        int maxit, int fixed_iters, bp_pcg_stats *st, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!valid_which(which)) return set_error(BP_ERR_ARG, "bp_pcg_solve_static: which");
+  if (!b || !x) return set_error(BP_ERR_ARG, "bp_pcg_solve_static: NULL vector");
+  if (maxit < 0 || !(rtol >= 0.0)) return set_error(BP_ERR_ARG, "bp_pcg_solve_static: maxit/rtol");
+  const size_t need = scratch_layout(op, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (need > kStaticWsBytes)
+    return set_error(BP_ERR_ARG, "bp_pcg_solve_static: the operator needs " +
+                                     std::to_string(need) + " bytes of workspace, the static "
+                                     "workspace holds " + std::to_string(kStaticWsBytes) +
+                                     " (nglobal * ncomp up to about 2.7e6); use bp_pcg_solve");
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    base = g_scratch_ptr[op->device];
+  }
+  if (!base) return set_error(BP_ERR_HIP, "bp_pcg_solve_static: workspace not resolved");
+  CgWork ws{};
+  double *z = nullptr, *p = nullptr, *w = nullptr;
+  scratch_layout(op, static_cast<unsigned char *>(base), &ws, &z, &p, &w);
+  hipStream_t s = (hipStream_t)stream;
+  rc = ensure_dinv(op, which, s);
+  if (rc) return rc;
+  int iters = 0;
+  float ms = 0.0f;
+  double apply_ms = 0.0;
+  int apply_count = 0;
+  // standard recurrences whatever BP_OPT_CG_VARIANT says; every workspace
+  // word is written (w cleared, scalars uploaded) before it is read
+  rc = pcg_run<double>(op, ws, which, false, b, x, op->dinv[dinv_slot(op, which)], z, p, w, rtol,
+                       maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms, &apply_count);
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->iters = iters;
@@ -801,8 +921,9 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
     to_f32(op->r, op->b32, nv, s);
     fill_f32(op->x32, nv, 0.0f, s);
     int it = 0;
-    rc = pcg_run<float>(op, BP_STIFF, true, op->b32, op->x32, op->dinv32, op->r32, op->p32,
-                        op->w32, inner_rtol, max_inner, false, true, s, &it, nullptr);
+    rc = pcg_run<float>(op, own_work(op), BP_STIFF, true, op->b32, op->x32, op->dinv32,
+                        op->r32, op->p32, op->w32, inner_rtol, max_inner, false, true, s, &it,
+                        nullptr);
     if (rc) break;
     inner_total += it;
     dc_accumulate(nv, x, op->x32, s);
