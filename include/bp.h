@@ -55,6 +55,8 @@ enum bp_prec { BP_FP64 = 0, BP_FP32 = 1 };
 /* flags of bp_setup */
 #define BP_SETUP_FP32 1u      /* also keep single-precision geometric factors and
                                  workspace for prec = BP_FP32 and the mixed solve   */
+#define BP_SETUP_CALLER_ORDER 2u /* keep the caller's node numbering inside the
+                                 library (see bp_setup)                             */
 
 /* Version of this ABI (major*100 + minor). */
 int bp_version(void);
@@ -84,8 +86,20 @@ int bp_rule(int n, int quad, double *x, double *w);
  *     (placed at the GLL points of the reference element).
  *   dirichlet: host uint8 [nglobal] (nonzero = homogeneous Dirichlet node) or
  *     NULL (no Dirichlet nodes, e.g. BP1/BP2 with Neumann conditions).
- *   flags: 0 or BP_SETUP_FP32.
+ *   flags: 0 or a combination of BP_SETUP_FP32 and BP_SETUP_CALLER_ORDER.
  *   stream: stream for the uploads; bp_setup synchronises it before return.
+ * Internal node order: in a conforming mesh every element-interior node
+ * (local 0 < i, j, k < p) belongs to one element only. When the map shows
+ * this (every interior slot names a node that no other slot names; p >= 2)
+ * and BP_SETUP_CALLER_ORDER is not set, the library numbers its nodes
+ * internally: the interior nodes element by element in contiguous blocks,
+ * then the shared nodes in the order the elements first reach them. The
+ * operator kernels then read and write the interior nodes as contiguous
+ * blocks, with plain stores in place of atomic additions. Every entry point
+ * still takes and returns vectors in the caller's numbering: the vectors
+ * are permuted on entry and exit (one gather pass each, and a solve keeps
+ * its iteration in the internal order), and the results are the same up to
+ * the rounding order of the assembly sums.
  * With GL quadrature (and nelem p1^3 < 2^31) the operator also holds the
  * transposed gather map (int32, nglobal + 1 offsets and nelem p1^3 slots) and
  * an element-local output buffer of ncomp nelem p1^3 words (per precision):

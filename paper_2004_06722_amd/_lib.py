@@ -14,6 +14,7 @@ BP_MASS, BP_STIFF, BP_HELM = 1, 3, 4
 BP_FP64, BP_FP32 = 0, 1
 BP_MASKED = 1
 BP_SETUP_FP32 = 1
+BP_SETUP_CALLER_ORDER = 2
 BP_OPT_TIME_APPLY = 1
 BP_OPT_MIXED_MODE = 2
 BP_MIXED_RESTART, BP_MIXED_RELIABLE = 0, 1

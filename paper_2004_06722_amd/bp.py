@@ -13,7 +13,7 @@ import torch
 
 from . import _lib
 from ._lib import (BP_FP32, BP_FP64, BP_HELM, BP_MASKED, BP_MASS, BP_QUAD_GL, BP_QUAD_GLL,
-                   BP_SETUP_FP32, BP_STIFF, PcgStats, check)
+                   BP_SETUP_CALLER_ORDER, BP_SETUP_FP32, BP_STIFF, PcgStats, check)
 
 MASS, STIFF, HELM = BP_MASS, BP_STIFF, BP_HELM
 GL, GLL = BP_QUAD_GL, BP_QUAD_GLL
@@ -49,7 +49,7 @@ class Operator:
     """A mesh + order + quadrature on the current HIP device (bp_setup)."""
 
     def __init__(self, p: int, q: int, quad: int, elem_dofs, node_xyz, nglobal: int,
-                 dirichlet=None, ncomp: int = 1, fp32: bool = False):
+                 dirichlet=None, ncomp: int = 1, fp32: bool = False, caller_order: bool = False):
         self._lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device available")
@@ -72,7 +72,8 @@ class Operator:
         check(self._lib.bp_setup(ctypes.byref(h), p, q, quad, ncomp, self.nelem, self.nglobal,
                                  ed.ctypes.data, xyz.ctypes.data,
                                  None if dr is None else dr.ctypes.data,
-                                 BP_SETUP_FP32 if fp32 else 0, _stream()))
+                                 (BP_SETUP_FP32 if fp32 else 0)
+                                 | (BP_SETUP_CALLER_ORDER if caller_order else 0), _stream()))
         self._h = h
 
     # ------------------------------------------------------------------

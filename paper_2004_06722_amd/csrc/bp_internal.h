@@ -38,6 +38,19 @@ struct Basis {
 };
 Basis make_basis(int p, int q, int quad);
 
+// Internal node order. Every element-interior node (local (i, j, k) with
+// 0 < i, j, k < p1 - 1) of a conforming mesh belongs to that one element
+// alone, whatever the caller's numbering. If the map ed [nelem][p1^3] shows
+// this (each interior slot names a node referenced exactly once), the
+// interior nodes are numbered first, element by element in local order
+// ([0, *n_owned)), then every other node in the order it is first met in
+// ed, then the nodes no element references; returns true and the
+// permutation both ways. Otherwise (p1 < 3, or an interior slot is shared)
+// returns false and the caller's order is kept.
+bool interior_first_order(int p1, int64_t nelem, int64_t nglobal, const int64_t *ed,
+                          std::vector<int32_t> &new_of_old, std::vector<int32_t> &old_of_new,
+                          int64_t *n_owned);
+
 // ---- device-side scalars of the CG iteration --------------------------------
 constexpr int kMaxComp = 8;
 constexpr int kMaxTimedApplies = 4096;
@@ -94,6 +107,13 @@ struct bp_op_s {
   // tr_pos[tr_off[g] .. tr_off[g + 1]), ascending) and the element-local
   // output wl [ncomp][nelem][p1^3] of the mass kernel (wl32 in FP32)
   int32_t *tr_off = nullptr, *tr_pos = nullptr;
+  // internal node order (interior_first_order): perm[v] = the caller's id of
+  // internal node v (NULL: the caller's order); internal nodes [0, n_owned)
+  // are element-interior, each written by its element with a plain store;
+  // bi, xi: b and x of a solve in the internal order
+  int32_t *perm = nullptr;
+  int64_t n_owned = 0;
+  double *bi = nullptr, *xi = nullptr;
   double *wl = nullptr;
   float *wl32 = nullptr;
   std::vector<hipEvent_t> apply_ev;  // pairs around operator launches

@@ -80,6 +80,9 @@ void release(bp_op op) {
   dfree(op->sv);
   dfree(op->tr_off);
   dfree(op->tr_pos);
+  dfree(op->perm);
+  dfree(op->bi);
+  dfree(op->xi);
   dfree(op->wl);
   dfree(op->wl32);
   dfree(op->r32);
@@ -246,6 +249,14 @@ int upload_scalars(bp_op op, double rtol, bool fixed, hipStream_t s) {
 }
 int download_scalars(bp_op op, hipStream_t s) { return download_scalars(op, op->sc, s); }
 
+// Nodes [0, n) whose w the operator for `which` overwrites with plain stores
+// on every application (the element-interior block of the internal order),
+// so the vector updates need not clear them. The Gauss-Legendre mass
+// assembles w by adding Q^T w_L (gather_local) and needs w cleared.
+int64_t stored_rows(const bp_op_s *op, int which) {
+  return which == BP_MASS && op->tr_off ? 0 : op->n_owned;
+}
+
 // Jacobi-PCG on precision T. x0_zero: x is zero on entry (skips A x0).
 // The buffer `r` holds the preconditioned residual z = dinv r during the
 // iteration (ten vector words per DOF and iteration; see k_cg_init).
@@ -306,7 +317,7 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
         cg_update_r_gather<T>(nc, n, nl, r, wl, op->tr_off, op->tr_pos, dinv, part, sc, s,
                               check);
       else
-        cg_update_r<T>(nc, n, r, w, dinv, part, sc, s, check);
+        cg_update_r<T>(nc, n, r, w, dinv, part, sc, s, check, stored_rows(op, which));
       cg_fin_beta(nc, nb_vec, part, sc, s, check);
       cg_update_xp<T>(nc, n, x, p, r, sc, s, check);
     }
@@ -376,7 +387,8 @@ int pcg_run_sr(bp_op op, int which, const double *b, double *x, const double *di
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
     for (int c = 0; c < chunk; ++c) {
-      sr_update<double>(nc, n, x, u, w, p, sv, dinv, pv, op->sc, s, check);
+      sr_update<double>(nc, n, x, u, w, p, sv, dinv, pv, op->sc, s, check,
+                        stored_rows(op, which));
       // the operator and finisher of the last fixed iteration would only
       // prepare a step that is not taken
       if (fixed && it + c == maxit - 1) break;
@@ -482,6 +494,30 @@ int mixed_reliable(bp_op op, const double *b, double *x, double rtol, double del
   return rc;
 }
 
+// The b and x a solve iterates on: the caller's (caller order), or the
+// internal copies bi, xi with b and x0 permuted into them.
+struct SolveVectors {
+  const double *b;
+  double *x;
+};
+
+SolveVectors solve_in(bp_op op, const double *b, double *x, hipStream_t s) {
+  if (!op->perm) return SolveVectors{b, x};
+  permute_in<double>(op->ncomp, op->nglobal, op->perm, b, op->bi, s);
+  permute_in<double>(op->ncomp, op->nglobal, op->perm, x, op->xi, s);
+  return SolveVectors{op->bi, op->xi};
+}
+
+// the solution back into the caller's x (nothing to do in the caller's
+// order); the stream is synchronised, as the solves promise
+int solve_out(bp_op op, double *x, hipStream_t s) {
+  if (!op->perm) return BP_OK;
+  permute_out<double>(op->ncomp, op->nglobal, op->perm, op->xi, x, s);
+  BP_HIP(hipGetLastError());
+  BP_HIP(hipStreamSynchronize(s));
+  return BP_OK;
+}
+
 void fill_stats(bp_op op, double rtol, bp_pcg_stats *st) {
   if (!st) return;
   st->ncomp = op->ncomp;
@@ -536,7 +572,8 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   if (nglobal < 1 || nglobal > 2147483647LL)
     return set_error(BP_ERR_ARG, "bp_setup: nglobal must be in [1, 2^31 - 1]");
   if (!elem_dofs || !node_xyz) return set_error(BP_ERR_ARG, "bp_setup: NULL mesh array");
-  if (flags & ~BP_SETUP_FP32) return set_error(BP_ERR_ARG, "bp_setup: unknown flag");
+  if (flags & ~(BP_SETUP_FP32 | BP_SETUP_CALLER_ORDER))
+    return set_error(BP_ERR_ARG, "bp_setup: unknown flag");
   if (!kernels_cover(p, q, quad))
     return set_error(BP_ERR_ARG, "bp_setup: no compiled kernels for p=" + std::to_string(p) +
                                      ", q=" + std::to_string(q) +
@@ -545,16 +582,26 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   const int p1 = p + 1;
   const int64_t n3 = (int64_t)p1 * p1 * p1, nq = (int64_t)q * q * q;
 
-  // gather map with the Dirichlet sign encoding
-  std::vector<int32_t> idx((size_t)(nelem * n3));
   for (int64_t k = 0; k < nelem * n3; ++k) {
     const int64_t g = elem_dofs[k];
     if (g < 0 || g >= nglobal)
       return set_error(BP_ERR_MESH, "bp_setup: elem_dofs entry " + std::to_string(k) + " = " +
                                         std::to_string(g) + " out of range (element " +
                                         std::to_string(k / n3) + ")");
+  }
+  // internal node order: element-interior nodes first, in per-element blocks
+  std::vector<int32_t> new_of_old, old_of_new;
+  int64_t n_owned = 0;
+  const bool renum = !(flags & BP_SETUP_CALLER_ORDER) &&
+                     interior_first_order(p1, nelem, nglobal, elem_dofs, new_of_old, old_of_new,
+                                          &n_owned);
+  // gather map in internal ids with the Dirichlet sign encoding
+  std::vector<int32_t> idx((size_t)(nelem * n3));
+  for (int64_t k = 0; k < nelem * n3; ++k) {
+    const int64_t g = elem_dofs[k];
+    const int32_t v = renum ? new_of_old[(size_t)g] : (int32_t)g;
     const bool dir = dirichlet && dirichlet[g];
-    idx[k] = dir ? (int32_t)(-1 - g) : (int32_t)g;
+    idx[k] = dir ? -1 - v : v;
   }
 
   bp_op op = new bp_op_s();
@@ -600,17 +647,27 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRY(dmalloc(&op->idx, idx.size()));
   TRYHIP(hipMemcpyAsync(op->idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   TRYHIP(hipStreamSynchronize(s));
+  if (renum) {
+    op->n_owned = n_owned;
+    TRY(dmalloc(&op->perm, old_of_new.size()));
+    TRYHIP(hipMemcpyAsync(op->perm, old_of_new.data(), old_of_new.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    TRYHIP(hipStreamSynchronize(s));
+    TRY(dmalloc(&op->bi, nv));
+    TRY(dmalloc(&op->xi, nv));
+  }
   // Gauss-Legendre operators: the transposed gather map (counting sort of the
   // element-local slots by global node, ascending within a node) for the
   // mass operator's fixed-order assembly, and its element-local output
   const int64_t nl = nelem * n3;
   if (!op->colloc && nl < (int64_t(1) << 31)) {
+    auto node = [&](int64_t k) -> size_t { return (size_t)(idx[k] >= 0 ? idx[k] : -1 - idx[k]); };
     std::vector<int32_t> off((size_t)nglobal + 1, 0), pos((size_t)nl);
-    for (int64_t k = 0; k < nl; ++k) ++off[(size_t)elem_dofs[k] + 1];
+    for (int64_t k = 0; k < nl; ++k) ++off[node(k) + 1];
     for (int64_t g = 0; g < nglobal; ++g) off[(size_t)g + 1] += off[(size_t)g];
     {
       std::vector<int32_t> cur(off.begin(), off.end() - 1);
-      for (int64_t k = 0; k < nl; ++k) pos[(size_t)cur[(size_t)elem_dofs[k]]++] = (int32_t)k;
+      for (int64_t k = 0; k < nl; ++k) pos[(size_t)cur[node(k)]++] = (int32_t)k;
     }
     TRY(dmalloc(&op->tr_off, off.size()));
     TRY(dmalloc(&op->tr_pos, pos.size()));
@@ -767,13 +824,32 @@ int bp_apply(bp_op op, int which, int prec, const void *u, void *w, unsigned fla
   if (u == w) return set_error(BP_ERR_ARG, "bp_apply: w must not alias u");
   if (flags & ~BP_MASKED) return set_error(BP_ERR_ARG, "bp_apply: unknown flag");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t nv = op->nglobal * op->ncomp;
-  if (prec == BP_FP32)
-    fill_f32((float *)w, nv, 0.0f, s);
-  else
-    fill_f64((double *)w, nv, 0.0, s);
-  return launch_apply(op, which, prec == BP_FP32, u, w, (flags & BP_MASKED) != 0, nullptr,
-                      nullptr, s);
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal, nv = n * nc;
+  const bool f32 = prec == BP_FP32, masked = (flags & BP_MASKED) != 0;
+  if (!op->perm) {
+    if (f32)
+      fill_f32((float *)w, nv, 0.0f, s);
+    else
+      fill_f64((double *)w, nv, 0.0, s);
+    return launch_apply(op, which, f32, u, w, masked, nullptr, nullptr, s);
+  }
+  // internal order: u in, the operator on the operator's work vectors, w out
+  if (f32) {
+    permute_in<float>(nc, n, op->perm, (const float *)u, op->r32, s);
+    fill_f32(op->w32, nv, 0.0f, s);
+    rc = launch_apply(op, which, true, op->r32, op->w32, masked, nullptr, nullptr, s);
+    if (rc) return rc;
+    permute_out<float>(nc, n, op->perm, op->w32, (float *)w, s);
+  } else {
+    permute_in<double>(nc, n, op->perm, (const double *)u, op->r, s);
+    fill_f64(op->w, nv, 0.0, s);
+    rc = launch_apply(op, which, false, op->r, op->w, masked, nullptr, nullptr, s);
+    if (rc) return rc;
+    permute_out<double>(nc, n, op->perm, op->w, (double *)w, s);
+  }
+  BP_HIP(hipGetLastError());
+  return BP_OK;
 }
 
 int bp_apply_local(bp_op op, int which, int prec, const void *uL, void *wL, void *stream) {
@@ -795,8 +871,13 @@ int bp_diag(bp_op op, int which, double *d, unsigned flags, void *stream) {
   if (!d) return set_error(BP_ERR_ARG, "bp_diag: NULL output");
   if (flags & ~BP_MASKED) return set_error(BP_ERR_ARG, "bp_diag: unknown flag");
   hipStream_t s = (hipStream_t)stream;
-  fill_f64(d, op->nglobal, 0.0, s);
-  return launch_diag(op, which, d, (flags & BP_MASKED) != 0, s);
+  double *dd = op->perm ? op->tmp : d;  // internal order: through op->tmp
+  fill_f64(dd, op->nglobal, 0.0, s);
+  rc = launch_diag(op, which, dd, (flags & BP_MASKED) != 0, s);
+  if (rc || !op->perm) return rc;
+  permute_out<double>(1, op->nglobal, op->perm, dd, d, s);
+  BP_HIP(hipGetLastError());
+  return BP_OK;
 }
 
 int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, int maxit,
@@ -813,14 +894,17 @@ int bp_pcg_solve(bp_op op, int which, const double *b, double *x, double rtol, i
   float ms = 0.0f;
   double apply_ms = 0.0;
   int apply_count = 0;
+  const SolveVectors v = solve_in(op, b, x, s);
   if (op->cg_variant == BP_CG_SINGLE_REDUCTION) {
-    rc = pcg_run_sr(op, which, b, x, op->dinv[dinv_slot(op, which)], rtol, maxit, fixed_iters != 0,
-                    false, s, &iters, &ms, &apply_ms, &apply_count);
+    rc = pcg_run_sr(op, which, v.b, v.x, op->dinv[dinv_slot(op, which)], rtol, maxit,
+                    fixed_iters != 0, false, s, &iters, &ms, &apply_ms, &apply_count);
   } else {
-    rc = pcg_run<double>(op, own_work(op), which, false, b, x, op->dinv[dinv_slot(op, which)],
-                         op->r, op->pv, op->w, rtol, maxit, fixed_iters != 0, false, s, &iters,
-                         &ms, &apply_ms, &apply_count);
+    rc = pcg_run<double>(op, own_work(op), which, false, v.b, v.x,
+                         op->dinv[dinv_slot(op, which)], op->r, op->pv, op->w, rtol, maxit,
+                         fixed_iters != 0, false, s, &iters, &ms, &apply_ms, &apply_count);
   }
+  const int rc_out = solve_out(op, x, s);
+  if (rc == BP_OK) rc = rc_out;
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->iters = iters;
@@ -863,8 +947,12 @@ int bp_pcg_solve_static(bp_op op, int which, const double *b, double *x, double 
   int apply_count = 0;
   // standard recurrences whatever BP_OPT_CG_VARIANT says; every workspace
   // word is written (w cleared, scalars uploaded) before it is read
-  rc = pcg_run<double>(op, ws, which, false, b, x, op->dinv[dinv_slot(op, which)], z, p, w, rtol,
-                       maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms, &apply_count);
+  const SolveVectors v = solve_in(op, b, x, s);
+  rc = pcg_run<double>(op, ws, which, false, v.b, v.x, op->dinv[dinv_slot(op, which)], z, p, w,
+                       rtol, maxit, fixed_iters != 0, false, s, &iters, &ms, &apply_ms,
+                       &apply_count);
+  const int rc_out = solve_out(op, x, s);
+  if (rc == BP_OK) rc = rc_out;
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->iters = iters;
@@ -876,9 +964,10 @@ int bp_pcg_solve_static(bp_op op, int which, const double *b, double *x, double 
   return rc;
 }
 
-int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
+int bp_pcg_solve_mixed(bp_op op, const double *b, double *x_out, double outer_rtol,
                        double inner_rtol, int max_outer, int max_inner, bp_pcg_stats *st,
                        void *stream) {
+  double *x = x_out;
   int rc = check_op(op);
   if (rc) return rc;
   if (!op->fp32) return set_error(BP_ERR_ARG, "bp_pcg_solve_mixed: needs BP_SETUP_FP32");
@@ -893,6 +982,9 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
   const bool masked = op->has_dirichlet;
   // the events were created by bp_setup: the solve allocates nothing
   hipEvent_t t0 = op->evm0, t1 = op->evm1;
+  const SolveVectors v = solve_in(op, b, x, s);
+  b = v.b;
+  x = v.x;
   BP_HIP(hipEventRecord(t0, s));
   int outer = 0, inner_total = 0;
   if (op->mixed_mode == BP_MIXED_RELIABLE) {
@@ -930,6 +1022,8 @@ int bp_pcg_solve_mixed(bp_op op, const double *b, double *x, double outer_rtol,
     ++outer;
   }
   BP_HIP(hipEventRecord(t1, s));
+  const int rc_out = solve_out(op, x_out, s);
+  if (rc == BP_OK) rc = rc_out;
   BP_HIP(hipEventSynchronize(t1));
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, t0, t1);
@@ -947,7 +1041,14 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g, void 
   int rc = check_op(op);
   if (rc) return rc;
   if (!lam || !u || !g) return set_error(BP_ERR_ARG, "bp_grad_kappa: NULL pointer");
-  return launch_grad_kappa(op, lam, u, g, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if (op->perm) {  // internal order: lam and u through the operator's work vectors
+    permute_in<double>(op->ncomp, op->nglobal, op->perm, lam, op->r, s);
+    permute_in<double>(op->ncomp, op->nglobal, op->perm, u, op->pv, s);
+    lam = op->r;
+    u = op->pv;
+  }
+  return launch_grad_kappa(op, lam, u, g, s);
 }
 
 int bp_set_option(bp_op op, int option, int value) {

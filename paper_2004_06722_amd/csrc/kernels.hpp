@@ -75,6 +75,15 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *out, in
     }
 }
 
+// Element-interior local node (0 < i, j, k < P1 - 1): with the internal node
+// order (own != 0) no other element touches it, so the scatter stores its
+// value instead of adding it atomically (its internal id lies in a block of
+// the element's own, on cache lines no atomic touches).
+template <int P1>
+__device__ __forceinline__ bool interior_node(int i, int j, int k) {
+  return i > 0 && i < P1 - 1 && j > 0 && j < P1 - 1 && k > 0 && k < P1 - 1;
+}
+
 // Decoded gather index: global id, or -1 when the node is skipped
 // (element slot not live, or a Dirichlet node under the mask).
 __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
@@ -108,7 +117,7 @@ template <int P1, typename T, bool LOCAL = false, bool HELM = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *Dg,
     const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
-    int masked, double *__restrict__ part, const int *__restrict__ done) {
+    int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
   constexpr int NC = 1;  // one component per launch; G is re-read per component
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
@@ -235,8 +244,8 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
         acc += sDt[j][m] * ss[slot][c][k][m][i];
       }
       if (mb >> k & 1u) {
-        if constexpr (LOCAL)
-          w[gk[k]] = acc;  // element-local output: no assembly
+        if (LOCAL || (own && interior_node<P1>(i, j, k)))
+          w[gk[k]] = acc;  // element-local output, or a node of this element alone
         else
           atomic_add(w + gk[k], acc);
       }
@@ -253,7 +262,7 @@ template <int P1, typename T, bool LOCAL = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Bt,
     const T *__restrict__ u, T *__restrict__ w, int64_t cstride, int ncomp, int masked,
-    double *__restrict__ part, const int *__restrict__ done) {
+    double *__restrict__ part, const int *__restrict__ done, int own) {
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1;
   if (done && *done) return;
@@ -261,6 +270,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
   const bool act = t < PL::USED;
   const int slot = act ? t / PL::N : 0;
   const int ij = t % PL::N;
+  const int i = ij % P1, j = ij / P1;
   const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
   const bool live = act && e < nelem;
   int gk[P1];
@@ -284,7 +294,7 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
       const T uv = u[o];
       const T wv = b[k] * uv;
       en[0] += (double)uv * (double)wv;
-      if constexpr (LOCAL)
+      if (LOCAL || (own && interior_node<P1>(i, j, k)))
         w[o] = wv;
       else
         atomic_add(w + o, wv);
@@ -448,7 +458,7 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
     const T *__restrict__ Bb, const T *__restrict__ basis, const T *__restrict__ u,
     T *__restrict__ w, int ncomp, int c0, int masked, double *__restrict__ part,
-    const int *__restrict__ done) {
+    const int *__restrict__ done, int own) {
   using PL = GLPlane<P1, Q, MODE>;
   using EO = EvenOdd<Q, P1>;
   constexpr bool STIFF = MODE != kGLMass, HELM = MODE == kGLHelm;
@@ -698,7 +708,10 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
         // w_L of the element (0 at skipped nodes); the caller applies Q^T
         if (live) w[ec * N3 + ci + P1 * (cj + P1 * k)] = (mb >> k & 1u) ? wk[k] : T(0);
       } else if (mb >> k & 1u) {
-        atomic_add(w + gk[k], wk[k]);
+        if (own && interior_node<P1>(ci, cj, k))
+          w[gk[k]] = wk[k];  // a node of this element alone
+        else
+          atomic_add(w + gk[k], wk[k]);
       }
     }
   }

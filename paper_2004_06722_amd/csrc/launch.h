@@ -69,9 +69,11 @@ void cg_init(int nc, int64_t n, const T *b, T *r, T *w, T *p, const T *dinv, dou
 // the done flag, so their loads need not wait for it
 void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStream_t s,
                   bool check = true);
+// n_own: nodes [0, n_own) are written whole by the operator (internal
+// order), so w is cleared from n_own on
 template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
-                 hipStream_t s, bool check = true);
+                 hipStream_t s, bool check = true, int64_t n_own = 0);
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
                  bool check = true);
 template <typename T>
@@ -99,7 +101,15 @@ void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const
              double *part, hipStream_t s);
 template <typename T>
 void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
-               DevScalars *sc, hipStream_t s, bool check = true);
+               DevScalars *sc, hipStream_t s, bool check = true, int64_t n_own = 0);
+
+// vectors [nc][n] between the caller's node order and the internal one
+// (perm[v] = the caller's id of internal node v): dst[c][v] = src[c][perm[v]]
+// (in), dst[c][perm[v]] = src[c][v] (out)
+template <typename T>
+void permute_in(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s);
+template <typename T>
+void permute_out(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s);
 void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba,
             DevScalars *sc, hipStream_t s);
 

@@ -30,6 +30,10 @@ int64_t max_partial_rows(const bp_op_s *op) {
 
 namespace {
 
+// 1 when the internal node order gives the element-interior nodes to their
+// element alone (plain stores in the scatter)
+int owned(const bp_op_s *op) { return op->n_owned > 0 ? 1 : 0; }
+
 // Component stride of the vectors a launch reads and writes: global vectors
 // [ncomp][nglobal], or element-local vectors [ncomp][nelem][p1^3] (LOCAL).
 template <bool LOCAL>
@@ -46,7 +50,7 @@ int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *Bb, con
   for (int c = 0; c < op->ncomp; ++c)
     hipLaunchKernelGGL((k_stiff_colloc<P1, T, LOCAL, HELM>), dim3(apply_blocks(op)),
                        dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Dg, Bb, u + c * cs,
-                       w + c * cs, op->ncomp, c, masked, part, done);
+                       w + c * cs, op->ncomp, c, masked, part, done, owned(op));
   return BP_OK;
 }
 
@@ -56,7 +60,7 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
   using PL = Plane<P1, P1>;
   hipLaunchKernelGGL((k_mass_colloc<P1, T, LOCAL>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0,
                      s, op->nelem, op->idx, Bt, u, w, vec_stride<LOCAL>(op), op->ncomp, masked,
-                     part, done);
+                     part, done, owned(op));
   return BP_OK;
 }
 
@@ -73,7 +77,7 @@ int gauss(const bp_op_s *op, const T *Gm, const T *Bb, const T *basis, const T *
   for (int c = 0; c < op->ncomp; ++c)
     hipLaunchKernelGGL((k_op_gl<P1, Q, T, MODE, LOCAL, WL>), dim3(grid), dim3(PL::THREADS), 0,
                        s, op->nelem, op->idx, Gm, Bb, basis, u + c * cs, w + c * ws, op->ncomp,
-                       c, masked, part, done);
+                       c, masked, part, done, owned(op));
   return BP_OK;
 }
 

@@ -263,10 +263,13 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
 // reads p anyway: five vector words here and five there.
 // check = 0 (a fixed number of iterations): no early exit on the done flag,
 // so the loads do not wait for it (likewise in the other iteration kernels).
+// Nodes below n_own are element-interior nodes in the internal order (see
+// interior_first_order): the operator overwrites their w with plain stores,
+// so w is cleared only from n_own on (likewise in k_sr_update).
 template <typename T, bool NT>
 __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r(
     int64_t n, T *__restrict__ z, T *__restrict__ w, const T *__restrict__ dinv,
-    double *__restrict__ part, const DevScalars *__restrict__ sc, int check) {
+    double *__restrict__ part, const DevScalars *__restrict__ sc, int check, int64_t n_own) {
   constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
   if (check && sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r(
       const int64_t f = comp * n + v;
       const T zv = zo[j] - (al * di[j]) * wo[j];
       st_v<NT>(z + f, zv);
-      st_v<NT>(w + f, T(0));
+      if (v >= n_own) st_v<NT>(w + f, T(0));
       const T rv = di[j] != T(0) ? zv / di[j] : T(0);
       rz += (double)rv * (double)zv;
       rr += (double)rv * (double)rv;
@@ -582,7 +585,7 @@ template <typename T, bool NT>
 __global__ __launch_bounds__(kGroupThreads<T>) void k_sr_update(
     int64_t n, T *__restrict__ x, T *__restrict__ u, T *__restrict__ w, T *__restrict__ p,
     T *__restrict__ sv, const T *__restrict__ dinv, double *__restrict__ part,
-    const DevScalars *__restrict__ sc, int check) {
+    const DevScalars *__restrict__ sc, int check, int64_t n_own) {
   constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
   if (check && sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_sr_update(
       const T rv = (di[j] != T(0) ? uo[j] / di[j] : T(0)) - al * s;
       const T uv = di[j] * rv;
       st_v<NT>(u + f, uv);
-      st_v<NT>(w + f, T(0));
+      if (v >= n_own) st_v<NT>(w + f, T(0));
       ru += (double)rv * (double)uv;
       rr += (double)rv * (double)rv;
     }
@@ -726,7 +729,42 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_mass(const double *__rest
   }
 }
 
+// Between the caller's node order and the internal one (perm[v] = the
+// caller's id of internal node v), per component: dst[c][v] = src[c][perm[v]]
+// (in) or dst[c][perm[v]] = src[c][v] (out).
+template <typename T, bool IN>
+__global__ __launch_bounds__(kVecThreads) void k_permute(int64_t n, const int32_t *__restrict__ perm,
+                                                         const T *__restrict__ src,
+                                                         T *__restrict__ dst) {
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (v >= n) return;
+  const int64_t c = (int64_t)blockIdx.y * n, g = perm[v];
+  if constexpr (IN)
+    dst[c + v] = src[c + g];
+  else
+    dst[c + g] = src[c + v];
+}
+
 }  // namespace
+
+template <typename T>
+void permute_in(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_permute<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n,
+                     perm, src, dst);
+}
+template <typename T>
+void permute_out(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_permute<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n,
+                     perm, src, dst);
+}
+template void permute_in<double>(int, int64_t, const int32_t *, const double *, double *,
+                                 hipStream_t);
+template void permute_in<float>(int, int64_t, const int32_t *, const float *, float *,
+                                hipStream_t);
+template void permute_out<double>(int, int64_t, const int32_t *, const double *, double *,
+                                  hipStream_t);
+template void permute_out<float>(int, int64_t, const int32_t *, const float *, float *,
+                                 hipStream_t);
 
 int64_t vec_blocks(int64_t n) {
   const int64_t b = (n + kVecThreads - 1) / kVecThreads;
@@ -864,13 +902,15 @@ void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStr
 
 template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
-                 hipStream_t s, bool check) {
+                 hipStream_t s, bool check, int64_t n_own) {
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
     hipLaunchKernelGGL((k_cg_update_r<T, true>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0);
+                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0,
+                       n_own);
   else
     hipLaunchKernelGGL((k_cg_update_r<T, false>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0);
+                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0,
+                       n_own);
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
@@ -932,15 +972,15 @@ void sr_init(int nc, int64_t n, const T *b, T *r, T *w, T *u, T *p, T *sv, const
 
 template <typename T>
 void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
-               DevScalars *sc, hipStream_t s, bool check) {
+               DevScalars *sc, hipStream_t s, bool check, int64_t n_own) {
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
     hipLaunchKernelGGL((k_sr_update<T, true>), dim3(vec_blocks(n), nc),
                        dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc,
-                       check ? 1 : 0);
+                       check ? 1 : 0, n_own);
   else
     hipLaunchKernelGGL((k_sr_update<T, false>), dim3(vec_blocks(n), nc),
                        dim3(kGroupThreads<T>), 0, s, n, x, u, w, p, sv, dinv, part, sc,
-                       check ? 1 : 0);
+                       check ? 1 : 0, n_own);
 }
 
 template <int NC>
@@ -975,7 +1015,8 @@ void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba
 template void sr_init<double>(int, int64_t, const double *, double *, double *, double *,
                               double *, double *, const double *, double *, hipStream_t);
 template void sr_update<double>(int, int64_t, double *, double *, double *, double *, double *,
-                                const double *, double *, DevScalars *, hipStream_t, bool);
+                                const double *, double *, DevScalars *, hipStream_t, bool,
+                                int64_t);
 
 template <typename T>
 void cg_restart(int nc, int64_t n, T *r, T *p, const T *dinv, double *part,
@@ -1002,9 +1043,9 @@ template void cg_init<double>(int, int64_t, const double *, double *, double *, 
 template void cg_init<float>(int, int64_t, const float *, float *, float *, float *,
                              const float *, double *, DevScalars *, hipStream_t);
 template void cg_update_r<double>(int, int64_t, double *, double *, const double *, double *,
-                                  DevScalars *, hipStream_t, bool);
+                                  DevScalars *, hipStream_t, bool, int64_t);
 template void cg_update_r<float>(int, int64_t, float *, float *, const float *, double *,
-                                 DevScalars *, hipStream_t, bool);
+                                 DevScalars *, hipStream_t, bool, int64_t);
 template void cg_update_xp<double>(int, int64_t, double *, double *, const double *,
                                    DevScalars *, hipStream_t, bool);
 template void cg_update_xp<float>(int, int64_t, float *, float *, const float *, DevScalars *,

@@ -20,7 +20,7 @@ class Case:
     """Oracle Discretization + library Operator on one seeded mesh."""
 
     def __init__(self, bp, p, ex, ey, ez, seed=0, ncomp=1, fp32=False, dirichlet=None,
-                 scramble=None):
+                 scramble=None, caller_order=False):
         import paper_2004_06722_amd.bp as B
         self.bp, self.p, self.ncomp = bp, p, ncomp
         q, quad = B.bp_quadrature(bp, p)
@@ -43,7 +43,7 @@ class Case:
             lm = synth.scramble_mesh(lm, scramble)
         assert np.array_equal(lm.elem_dofs, om.elem_dofs)
         self.op = B.Operator(p, q, quad, lm.elem_dofs, lm.node_xyz, lm.nglobal,
-                             self.dir, ncomp=ncomp, fp32=fp32)
+                             self.dir, ncomp=ncomp, fp32=fp32, caller_order=caller_order)
 
     def vec(self, seed):
         v = synth.rhs_uniform(self.disc.nglobal, seed, ncomp=self.ncomp)
