@@ -280,7 +280,10 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
  *   its stream around every operator launch of the iteration loop (at most
  *   4096 pairs per solve) and reports their summed duration in
  *   bp_pcg_stats.apply_ms. Costs two event records per iteration; the events
- *   are created when the option is first set (BP_ERR_HIP if that fails).
+ *   are created when the option is first set (BP_ERR_HIP if that fails),
+ *   without the system-scope fence of a default event
+ *   (hipEventDisableSystemFence), so that recording them does not write back
+ *   and invalidate the caches around the timed kernels.
  * Unknown options return BP_ERR_ARG.
  */
 #define BP_OPT_TIME_APPLY 1

@@ -112,6 +112,7 @@ struct bp_op_s {
   // are element-interior, each written by its element with a plain store;
   // bi, xi: b and x of a solve in the internal order
   int32_t *perm = nullptr;
+  int32_t *iperm = nullptr;  // iperm[g] = the internal id of the caller's node g
   int64_t n_owned = 0;
   double *bi = nullptr, *xi = nullptr;
   double *wl = nullptr;

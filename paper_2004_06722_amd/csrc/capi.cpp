@@ -81,6 +81,7 @@ void release(bp_op op) {
   dfree(op->tr_off);
   dfree(op->tr_pos);
   dfree(op->perm);
+  dfree(op->iperm);
   dfree(op->bi);
   dfree(op->xi);
   dfree(op->wl);
@@ -188,6 +189,11 @@ struct CgWork {
 };
 
 CgWork own_work(bp_op op) { return CgWork{op->part, op->sc}; }
+
+// Flags of the library's timing events: without the system-scope release of
+// a default event, whose cache writeback and invalidation would slow the
+// timed kernels and those after them.
+constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
 
 // Device address of `scratch` on device dev (current), looked up once.
 int resolve_scratch(int dev) {
@@ -512,7 +518,7 @@ SolveVectors solve_in(bp_op op, const double *b, double *x, hipStream_t s) {
 // order); the stream is synchronised, as the solves promise
 int solve_out(bp_op op, double *x, hipStream_t s) {
   if (!op->perm) return BP_OK;
-  permute_out<double>(op->ncomp, op->nglobal, op->perm, op->xi, x, s);
+  permute_out<double>(op->ncomp, op->nglobal, op->iperm, op->xi, x, s);
   BP_HIP(hipGetLastError());
   BP_HIP(hipStreamSynchronize(s));
   return BP_OK;
@@ -650,7 +656,10 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   if (renum) {
     op->n_owned = n_owned;
     TRY(dmalloc(&op->perm, old_of_new.size()));
+    TRY(dmalloc(&op->iperm, new_of_old.size()));
     TRYHIP(hipMemcpyAsync(op->perm, old_of_new.data(), old_of_new.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    TRYHIP(hipMemcpyAsync(op->iperm, new_of_old.data(), new_of_old.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice, s));
     TRYHIP(hipStreamSynchronize(s));
     TRY(dmalloc(&op->bi, nv));
@@ -721,8 +730,11 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
   TRY(dmalloc(&op->part, op->part_len));
   TRY(dmalloc(&op->sc, 1));
   TRYHIP(hipHostMalloc((void **)&op->sc_host, sizeof(DevScalars), hipHostMallocDefault));
-  TRYHIP(hipEventCreate(&op->ev0));
-  TRYHIP(hipEventCreate(&op->ev1));
+  // timing events: no system-scope fence on record (no cache writeback and
+  // invalidation around the timed work; the solves synchronise the stream
+  // themselves before reading them)
+  TRYHIP(hipEventCreateWithFlags(&op->ev0, kTimingEvent));
+  TRYHIP(hipEventCreateWithFlags(&op->ev1, kTimingEvent));
   if (op->fp32) {
     TRY(dmalloc(&op->G32, ng));
     TRY(dmalloc(&op->Bt32, nb));
@@ -737,8 +749,8 @@ int bp_setup(bp_op *out, int p, int q, int quad, int ncomp, int64_t nelem, int64
     TRY(dmalloc(&op->b32, nv));
     TRY(dmalloc(&op->dinv32, nglobal));
     if (op->tr_off) TRY(dmalloc(&op->wl32, nl * ncomp));
-    TRYHIP(hipEventCreate(&op->evm0));
-    TRYHIP(hipEventCreate(&op->evm1));
+    TRYHIP(hipEventCreateWithFlags(&op->evm0, kTimingEvent));
+    TRYHIP(hipEventCreateWithFlags(&op->evm1, kTimingEvent));
   }
 #undef TRY
 #undef TRYHIP
@@ -840,13 +852,13 @@ int bp_apply(bp_op op, int which, int prec, const void *u, void *w, unsigned fla
     fill_f32(op->w32, nv, 0.0f, s);
     rc = launch_apply(op, which, true, op->r32, op->w32, masked, nullptr, nullptr, s);
     if (rc) return rc;
-    permute_out<float>(nc, n, op->perm, op->w32, (float *)w, s);
+    permute_out<float>(nc, n, op->iperm, op->w32, (float *)w, s);
   } else {
     permute_in<double>(nc, n, op->perm, (const double *)u, op->r, s);
     fill_f64(op->w, nv, 0.0, s);
     rc = launch_apply(op, which, false, op->r, op->w, masked, nullptr, nullptr, s);
     if (rc) return rc;
-    permute_out<double>(nc, n, op->perm, op->w, (double *)w, s);
+    permute_out<double>(nc, n, op->iperm, op->w, (double *)w, s);
   }
   BP_HIP(hipGetLastError());
   return BP_OK;
@@ -875,7 +887,7 @@ int bp_diag(bp_op op, int which, double *d, unsigned flags, void *stream) {
   fill_f64(dd, op->nglobal, 0.0, s);
   rc = launch_diag(op, which, dd, (flags & BP_MASKED) != 0, s);
   if (rc || !op->perm) return rc;
-  permute_out<double>(1, op->nglobal, op->perm, dd, d, s);
+  permute_out<double>(1, op->nglobal, op->iperm, dd, d, s);
   BP_HIP(hipGetLastError());
   return BP_OK;
 }
@@ -1058,7 +1070,7 @@ int bp_set_option(bp_op op, int option, int value) {
   if (option == BP_OPT_TIME_APPLY) {
     if (value && op->apply_ev.empty()) {
       op->apply_ev.resize(2 * kMaxTimedApplies, nullptr);
-      for (auto &ev : op->apply_ev) BP_HIP(hipEventCreate(&ev));
+      for (auto &ev : op->apply_ev) BP_HIP(hipEventCreateWithFlags(&ev, kTimingEvent));
     }
     op->time_apply = value != 0;
     return BP_OK;

@@ -103,13 +103,14 @@ template <typename T>
 void sr_update(int nc, int64_t n, T *x, T *u, T *w, T *p, T *sv, const T *dinv, double *part,
                DevScalars *sc, hipStream_t s, bool check = true, int64_t n_own = 0);
 
-// vectors [nc][n] between the caller's node order and the internal one
-// (perm[v] = the caller's id of internal node v): dst[c][v] = src[c][perm[v]]
-// (in), dst[c][perm[v]] = src[c][v] (out)
+// vectors [nc][n] between the caller's node order and the internal one,
+// both as gathers: in, dst[c][v] = src[c][perm[v]] (perm[v] = the caller's
+// id of internal node v); out, dst[c][g] = src[c][iperm[g]] (iperm[g] = the
+// internal id of the caller's node g)
 template <typename T>
 void permute_in(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s);
 template <typename T>
-void permute_out(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s);
+void permute_out(int nc, int64_t n, const int32_t *iperm, const T *src, T *dst, hipStream_t s);
 void sr_fin(bool first, int nc, double *pv, int64_t nbv, double *pa, int64_t nba,
             DevScalars *sc, hipStream_t s);
 

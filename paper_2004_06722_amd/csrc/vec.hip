@@ -729,33 +729,29 @@ __global__ __launch_bounds__(kVecThreads) void k_scale_mass(const double *__rest
   }
 }
 
-// Between the caller's node order and the internal one (perm[v] = the
-// caller's id of internal node v), per component: dst[c][v] = src[c][perm[v]]
-// (in) or dst[c][perm[v]] = src[c][v] (out).
-template <typename T, bool IN>
-__global__ __launch_bounds__(kVecThreads) void k_permute(int64_t n, const int32_t *__restrict__ perm,
+// Between the caller's node order and the internal one, per component, as a
+// gather (contiguous stores): dst[c][v] = src[c][map[v]].
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_permute(int64_t n, const int32_t *__restrict__ map,
                                                          const T *__restrict__ src,
                                                          T *__restrict__ dst) {
   const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   if (v >= n) return;
-  const int64_t c = (int64_t)blockIdx.y * n, g = perm[v];
-  if constexpr (IN)
-    dst[c + v] = src[c + g];
-  else
-    dst[c + g] = src[c + v];
+  const int64_t c = (int64_t)blockIdx.y * n;
+  dst[c + v] = src[c + map[v]];
 }
 
 }  // namespace
 
 template <typename T>
 void permute_in(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s) {
-  hipLaunchKernelGGL((k_permute<T, true>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n,
-                     perm, src, dst);
+  hipLaunchKernelGGL((k_permute<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, perm,
+                     src, dst);
 }
 template <typename T>
-void permute_out(int nc, int64_t n, const int32_t *perm, const T *src, T *dst, hipStream_t s) {
-  hipLaunchKernelGGL((k_permute<T, false>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n,
-                     perm, src, dst);
+void permute_out(int nc, int64_t n, const int32_t *iperm, const T *src, T *dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_permute<T>), dim3(vec_blocks(n), nc), dim3(kVecThreads), 0, s, n, iperm,
+                     src, dst);
 }
 template void permute_in<double>(int, int64_t, const int32_t *, const double *, double *,
                                  hipStream_t);

@@ -65,10 +65,18 @@ def local_apply_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) ->
     return E * (word * geometry_words(bp, p) + 2 * word * ncomp * (p + 1) ** 3)
 
 
-def iteration_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8) -> int:
-    """Bytes of one CG iteration (operator + vector updates)."""
+def iteration_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8,
+                    interior_order: bool = True) -> int:
+    """Bytes of one CG iteration (operator + vector updates). With the
+    library's internal node order (the default) the residual update does not
+    clear w on the (p-1)^3 element-interior nodes of each element, which the
+    operator overwrites with plain stores: one word less there. The Gauss-
+    Legendre mass (BP1/BP2) assembles by a gather and has no w to clear."""
     n = p ** 3 * E
-    return apply_bytes(bp, p, E, ncomp, word) + word * VECTOR_WORDS_CG * n * ncomp
+    b = apply_bytes(bp, p, E, ncomp, word) + word * VECTOR_WORDS_CG * n * ncomp
+    if interior_order and bp >= 3:
+        b -= word * max(p - 1, 0) ** 3 * E * ncomp
+    return b
 
 
 def work_direct(p1: int, gamma: float) -> float:
