@@ -62,7 +62,7 @@ def build_problem(bp: int, N: int, k: int, ncomp: int = 1, seed: int = 0, fp32: 
     return op, bd, info
 
 
-def time_solve(op, b, steps: int, warmup: int, reps: int = 1):
+def time_solve(op, b, steps: int, warmup: int, reps: int = 1, which: int = 3):
     """W warm-up iterations, then `reps` solves of exactly `steps` fixed
     iterations each, synchronised before and after. Returns per solve the
     host wall time around the call (it includes the solve's set-up: the
@@ -72,12 +72,12 @@ def time_solve(op, b, steps: int, warmup: int, reps: int = 1):
     the timing of section 2: the given number of CG iterations)."""
     import torch
     if warmup:
-        op.pcg_solve(b, maxit=warmup, fixed_iters=True)
+        op.pcg_solve(b, which=which, maxit=warmup, fixed_iters=True)
     walls, loops = [], []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, st = op.pcg_solve(b, maxit=steps, fixed_iters=True)
+        x, st = op.pcg_solve(b, which=which, maxit=steps, fixed_iters=True)
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
         loops.append(st["ms"] * 1e-3)
@@ -270,20 +270,16 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0, helm_beta=None):
     if helm_beta is not None:
         op.set_helmholtz(helm_beta)
         which = 4
-    if warmup:
-        op.pcg_solve(b, which=which, maxit=warmup, fixed_iters=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, st_t = op.pcg_solve(b, which=which, maxit=steps, fixed_iters=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # operator average from a second run with per-launch events (the events
-    # themselves add gaps to the iteration, so they stay out of the timed run)
+    walls, loops, _ = time_solve(op, b, steps, warmup, reps=3, which=which)
+    loop, wall = median(loops), median(walls)
+    # operator average from a second run with per-launch events (they stay
+    # out of the timed runs)
     op.set_option(BP_OPT_TIME_APPLY, 1)
     _, st = op.pcg_solve(b, which=which, maxit=min(steps, 30), fixed_iters=True)
     op.close()
     E, n = info["E"], info["n"]
-    log(f"BP{bp} N={N} E={E} ncomp={ncomp}: {steps} iterations in {wall * 1e3:.1f} ms")
+    log(f"BP{bp} N={N} E={E} ncomp={ncomp}: {steps} iterations in {loop * 1e3:.1f} ms "
+        f"(median of 3; wall {wall * 1e3:.1f} ms)")
     apply_ms = st["apply_ms"] / max(st["apply_count"], 1)
     if helm_beta is not None:
         ab = model.helm_apply_bytes(bp, N, E, ncomp)
@@ -293,12 +289,13 @@ def run_fixed(bp, N, grid, ncomp, steps=100, warmup=10, seed=0, helm_beta=None):
         ab = model.apply_bytes(bp, N, E, ncomp)
     return {"bp": bp, "helm_beta": helm_beta, "N": N, "E": E, "ncomp": ncomp, "n": n,
             "n_unique": info["n_unique"],
-            "iters": steps, "wall_ms": wall * 1e3, "ms_per_iter": wall * 1e3 / steps,
-            "DOFs_per_s": steps * n * ncomp / wall,
+            "iters": steps, "loop_ms": loop * 1e3, "wall_ms": wall * 1e3,
+            "ms_per_iter": loop * 1e3 / steps, "DOFs_per_s": steps * n * ncomp / loop,
+            "DOFs_per_s_wall": steps * n * ncomp / wall,
             "apply_avg_ms": apply_ms, "apply_alg_GBs": ab / (apply_ms * 1e-3) / 1e9,
             "apply_frac_hbm": ab / (apply_ms * 1e-3) / 1e9 / model.HBM_PEAK_GBS,
             "iter_alg_frac_hbm": model.iteration_bytes(bp, N, E, ncomp) * steps
-                                 / (st_t["ms"] * 1e-3) / 1e9 / model.HBM_PEAK_GBS}
+                                 / loop / 1e9 / model.HBM_PEAK_GBS}
 
 
 def workload_vector(args):
@@ -306,6 +303,8 @@ def workload_vector(args):
     grid = (48, 48, 48)
     rows = []
     for sbp, vbp in ((1, 2), (3, 4), (5, 6)):
+        if vbp not in args.vector_bps:
+            continue
         s_rec = run_fixed(sbp, 7, grid, 1)
         log(f"BP{sbp}: {s_rec['DOFs_per_s']:.3e} DOFs/s")
         v_rec = run_fixed(vbp, 7, grid, 3, seed=0)
@@ -582,6 +581,8 @@ def main():
                     help="sweep13: which orders N")
     ap.add_argument("--cg", default="standard", choices=["standard", "single-reduction"],
                     help="PCG recurrences of the bp5 workload and its sweep")
+    ap.add_argument("--vector-bps", type=int, nargs="+", default=[2, 4, 6],
+                    help="vector workload: which vector BPs (each with its scalar BP)")
     ap.add_argument("--bk", type=int, default=5, choices=[1, 3, 5],
                     help="bk workload: which bake-off kernel")
     ap.add_argument("--workload", default="bp5",

@@ -92,33 +92,16 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
   return masked ? -1 : -1 - v;
 }
 
-// ---------------------------------------------------------------------------
-// BK5/BK6: stiffness with collocated GLL quadrature (J^ = I, q = p1).
-// One component per launch: u and w point at component c0 (vectors are
-// component-major, [ncomp][nglobal]); ncomp and c0 place the energy partial. Keeping
-// the G column in registers across several components doubles the register
-// footprint and halves occupancy, which costs more than re-reading G.
-//
-// Arithmetic is not the limit (HBM traffic and the rate of the atomic
-// scatter are), so the kernel is laid out to need few dependent round trips:
-// each lane requests its whole column of G (6 x p1 values) and of the gather
-// map at entry, then gathers u, then computes from registers and LDS. The k direction stays in registers; the r and s contractions go
-// through LDS tiles. Loads are branch-free: an element slot past the end
-// reads the last element and a Dirichlet node reads its (valid) global
-// entry, both masked. Entries of D^ with compile-time indices
-// are scalar loads from Dg (global memory, D^[a][m] at a * p1 + m); the
-// lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
-// accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
-// HELM adds the Helmholtz term of eq. (hm2): with collocated GLL points the
-// mass matrix is diagonal, so w_L += (beta B~) u_L node by node, with the
-// beta-scaled B~ read beside G (one more word per point).
-// ---------------------------------------------------------------------------
-template <int P1, typename T, bool LOCAL = false, bool HELM = false>
-__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
-    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *Dg,
-    const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
-    int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
-  constexpr int NC = 1;  // one component per launch; G is re-read per component
+// Body of the collocated stiffness kernels (described below): with MULTI
+// every component of u and w ([ncomp][cs]) runs through one work-group, G and
+// the map loaded once; otherwise the one component that u and w point at
+// (energy column c0).
+template <int P1, typename T, bool LOCAL, bool HELM, bool MULTI>
+__device__ __forceinline__ void stiff_colloc_body(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *__restrict__ Dg,
+    const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int64_t cs, int ncomp,
+    int c0, int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
+  constexpr int NC = 1;  // LDS tiles of one component at a time
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
   if (done && *done) return;
@@ -166,92 +149,148 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
     if (!LOCAL) gk[k] = v >= 0 ? v : -1 - v;
   }
 
-  // gather u (requested before D^ is staged, so both wait together)
-  T ru[NC][P1];
+  const int nrun = MULTI ? ncomp : 1;
+#pragma unroll 1
+  for (int cc = 0; cc < nrun; ++cc) {
+    const T *uc = u + (MULTI ? cc * cs : 0);
+    T *wc = w + (MULTI ? cc * cs : 0);
+    // gather u
+    T ru[NC][P1];
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      const T v = u[gk[k]];
-      ru[c][k] = (mb >> k & 1u) ? v : T(0);
+      for (int k = 0; k < P1; ++k) {
+        const T v = uc[gk[k]];
+        ru[c][k] = (mb >> k & 1u) ? v : T(0);
+      }
+    if (cc == 0) {
+      // D^ staged after the first gather is requested, so both wait together
+      for (int x = t; x < PP; x += PL::THREADS) {
+        sD[x / P1][x % P1] = Dg[x];
+        sDt[x % P1][x / P1] = Dg[x];
+      }
+    } else {
+      __syncthreads();  // the tiles of the previous component have been read
     }
-  for (int x = t; x < PP; x += PL::THREADS) {
-    sD[x / P1][x % P1] = Dg[x];
-    sDt[x % P1][x / P1] = Dg[x];
-  }
 
-  // u into LDS; derivative along t (k) in registers
-  T rt[NC][P1];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-#pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      if (act) su[slot][c][k][j][i] = ru[c][k];
-      T s = 0;
-#pragma unroll
-      for (int m = 0; m < P1; ++m) s += Dg[k * P1 + m] * ru[c][m];
-      rt[c][k] = s;
-    }
-  }
-  __syncthreads();
-
-  // derivatives along r, s through LDS; apply G; energy at the points
-  double en[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) en[c] = 0.0;
-  if constexpr (HELM) {
-    if (act)
-#pragma unroll
-      for (int k = 0; k < P1; ++k) en[0] += (double)ru[0][k] * (double)(bb[k] * ru[0][k]);
-  }
-#pragma unroll
-  for (int k = 0; k < P1; ++k) {
+    // u into LDS; derivative along t (k) in registers
+    T rt[NC][P1];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      T ur = 0, us = 0;
 #pragma unroll
-      for (int m = 0; m < P1; ++m) {
-        ur += sD[i][m] * su[slot][c][k][j][m];
-        us += sD[j][m] * su[slot][c][k][m][i];
+      for (int k = 0; k < P1; ++k) {
+        if (act) su[slot][c][k][j][i] = ru[c][k];
+        T s = 0;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) s += Dg[k * P1 + m] * ru[c][m];
+        rt[c][k] = s;
       }
-      const T ut = rt[c][k];
-      const T vr = g[0][k] * ur + g[1][k] * us + g[2][k] * ut;
-      const T vs = g[1][k] * ur + g[3][k] * us + g[4][k] * ut;
-      const T vt = g[2][k] * ur + g[4][k] * us + g[5][k] * ut;
-      // idle lanes of a partly used wave read another element's tile: no energy
+    }
+    __syncthreads();
+
+    // derivatives along r, s through LDS; apply G; energy at the points
+    double en[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) en[c] = 0.0;
+    if constexpr (HELM) {
       if (act)
-        en[c] += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
-      rt[c][k] = vt;
-      if (act) {
-        sr[slot][c][k][j][i] = vr;
-        ss[slot][c][k][j][i] = vs;
+#pragma unroll
+        for (int k = 0; k < P1; ++k) en[0] += (double)ru[0][k] * (double)(bb[k] * ru[0][k]);
+    }
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T ur = 0, us = 0;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) {
+          ur += sD[i][m] * su[slot][c][k][j][m];
+          us += sD[j][m] * su[slot][c][k][m][i];
+        }
+        const T ut = rt[c][k];
+        const T vr = g[0][k] * ur + g[1][k] * us + g[2][k] * ut;
+        const T vs = g[1][k] * ur + g[3][k] * us + g[4][k] * ut;
+        const T vt = g[2][k] * ur + g[4][k] * us + g[5][k] * ut;
+        // idle lanes of a partly used wave read another element's tile: no energy
+        if (act)
+          en[c] += (double)ur * (double)vr + (double)us * (double)vs + (double)ut * (double)vt;
+        rt[c][k] = vt;
+        if (act) {
+          sr[slot][c][k][j][i] = vr;
+          ss[slot][c][k][j][i] = vs;
+        }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // transposed derivatives and scatter
+    // transposed derivatives and scatter
 #pragma unroll
-  for (int k = 0; k < P1; ++k) {
+    for (int k = 0; k < P1; ++k) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      T acc = 0;
-      if constexpr (HELM) acc = bb[k] * su[slot][c][k][j][i];
+      for (int c = 0; c < NC; ++c) {
+        T acc = 0;
+        if constexpr (HELM) acc = bb[k] * su[slot][c][k][j][i];
 #pragma unroll
-      for (int m = 0; m < P1; ++m) {
-        acc += Dg[m * P1 + k] * rt[c][m];
-        acc += sDt[i][m] * sr[slot][c][k][j][m];
-        acc += sDt[j][m] * ss[slot][c][k][m][i];
-      }
-      if (mb >> k & 1u) {
-        if (LOCAL || (own && interior_node<P1>(i, j, k)))
-          w[gk[k]] = acc;  // element-local output, or a node of this element alone
-        else
-          atomic_add(w + gk[k], acc);
+        for (int m = 0; m < P1; ++m) {
+          acc += Dg[m * P1 + k] * rt[c][m];
+          acc += sDt[i][m] * sr[slot][c][k][j][m];
+          acc += sDt[j][m] * ss[slot][c][k][m][i];
+        }
+        if (mb >> k & 1u) {
+          if (LOCAL || (own && interior_node<P1>(i, j, k)))
+            wc[gk[k]] = acc;  // element-local output, or a node of this element alone
+          else
+            atomic_add(wc + gk[k], acc);
+        }
       }
     }
+    if (part)
+      block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp +
+                                               (MULTI ? cc : c0), 1);
   }
-  if (part) block_sum_store<NC, PL::THREADS>(en, part + (int64_t)blockIdx.x * ncomp + c0, 1);
+}
+
+// ---------------------------------------------------------------------------
+// BK5/BK6: stiffness with collocated GLL quadrature (J^ = I, q = p1).
+// Vectors are component-major ([ncomp][nglobal]). k_stiff_colloc applies one
+// component (u and w point at component c0; ncomp and c0 place the energy
+// partial); k_stiff_colloc_nc applies all ncomp components of u and w
+// (component stride cs) in one launch: each work-group loads its element's G
+// column and map once and runs the components through the same LDS tiles
+// one after the other (BK6 and the vector problems), with at most 256
+// registers per lane so that two waves share each SIMD.
+//
+// Arithmetic is not the limit (HBM traffic and the rate of the atomic
+// scatter are), so the kernel is laid out to need few dependent round trips:
+// each lane requests its whole column of G (6 x p1 values) and of the gather
+// map at entry, then gathers u, then computes from registers and LDS. The k direction stays in registers; the r and s contractions go
+// through LDS tiles. Loads are branch-free: an element slot past the end
+// reads the last element and a Dirichlet node reads its (valid) global
+// entry, both masked. Entries of D^ with compile-time indices
+// are scalar loads from Dg (global memory, D^[a][m] at a * p1 + m); the
+// lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
+// accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
+// HELM adds the Helmholtz term of eq. (hm2): with collocated GLL points the
+// mass matrix is diagonal, so w_L += (beta B~) u_L node by node, with the
+// beta-scaled B~ read beside G (one more word per point). With the internal
+// node order (own) the element-interior nodes are stored, not added.
+// ---------------------------------------------------------------------------
+template <int P1, typename T, bool LOCAL = false, bool HELM = false>
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *__restrict__ Dg,
+    const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
+    int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
+  stiff_colloc_body<P1, T, LOCAL, HELM, false>(nelem, idx, G, Dg, Bb, u, w, 0, ncomp, c0, masked,
+                                               part, done, own);
+}
+
+template <int P1, typename T, bool LOCAL = false, bool HELM = false>
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS), 2) void k_stiff_colloc_nc(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *__restrict__ Dg,
+    const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int64_t cs,
+    int ncomp, int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
+  stiff_colloc_body<P1, T, LOCAL, HELM, true>(nelem, idx, G, Dg, Bb, u, w, cs, ncomp, 0, masked,
+                                              part, done, own);
 }
 
 // ---------------------------------------------------------------------------

@@ -41,12 +41,25 @@ int64_t vec_stride(const bp_op_s *op) {
   return LOCAL ? op->nelem * op->p1 * op->p1 * op->p1 : op->nglobal;
 }
 
+// Several components up to p = 7 (p = 6 with the Helmholtz term): one launch
+// of k_stiff_colloc_nc (G and the map read once per element for all of
+// them). Beyond, G beside a component's working set no longer fits 256
+// registers (the multi-component kernel spills), so each component gets its
+// own launch.
 template <int P1, typename T, bool LOCAL, bool HELM>
 int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *Bb, const T *u, T *w,
                  int masked, double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
   const T *Dg = basis + P1 * P1;  // D^ follows J^ (both p1 x p1 here)
   const int64_t cs = vec_stride<LOCAL>(op);
+  if constexpr (P1 <= (HELM ? 7 : 8)) {
+    if (op->ncomp > 1) {
+      hipLaunchKernelGGL((k_stiff_colloc_nc<P1, T, LOCAL, HELM>), dim3(apply_blocks(op)),
+                         dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Dg, Bb, u, w, cs,
+                         op->ncomp, masked, part, done, owned(op));
+      return BP_OK;
+    }
+  }
   for (int c = 0; c < op->ncomp; ++c)
     hipLaunchKernelGGL((k_stiff_colloc<P1, T, LOCAL, HELM>), dim3(apply_blocks(op)),
                        dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Dg, Bb, u + c * cs,
