@@ -379,6 +379,114 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r_gather(
   block_partial1<TH>(rr, part, 2 * nc, nc + comp);
 }
 
+// Partial sums of W values over the work-group in a fixed order: row
+// blockIdx.x of part[.][W] (one shuffle tree per wave, then the wave sums in
+// order; one barrier for all W).
+template <int W>
+__device__ __forceinline__ void block_partials(double (&v)[W], double *part) {
+  constexpr int NW = kVecThreads / 64;
+  __shared__ double red[NW][W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < W) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) x += red[k][threadIdx.x];
+    part[(int64_t)blockIdx.x * W + threadIdx.x] = x;
+  }
+}
+
+// The residual update for NC > 1 components: one thread per node for all
+// of them, so dinv is read once per node (the component-per-row grid of
+// k_cg_update_r reads it once per component). Partial columns as there:
+// r.z of component c in column c, r.r in column NC + c.
+template <typename T, bool NT, int NC>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_r_nc(
+    int64_t n, T *__restrict__ z, T *__restrict__ w, const T *__restrict__ dinv,
+    double *__restrict__ part, const DevScalars *__restrict__ sc, int check, int64_t n_own) {
+  if (check && sc->done) return;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double acc[2 * NC];
+#pragma unroll
+  for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
+  if (v < n) {
+    const T di = ld_v<NT>(dinv + v);
+    T zo[NC], wo[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      zo[c] = ld_v<NT>(z + c * n + v);
+      wo[c] = ld_v<NT>(w + c * n + v);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T zv = zo[c] - ((T)sc->alpha[c] * di) * wo[c];
+      st_v<NT>(z + c * n + v, zv);
+      if (v >= n_own) st_v<NT>(w + c * n + v, T(0));
+      const T rv = di != T(0) ? zv / di : T(0);
+      acc[c] = (double)rv * (double)zv;
+      acc[NC + c] = (double)rv * (double)rv;
+    }
+  }
+  block_partials<2 * NC>(acc, part);
+}
+
+// k_cg_update_r_gather for NC > 1 components: the node's offsets and slot
+// positions are read once and each component gathers its w_L through them
+// (the same fixed order per component).
+template <typename T, bool NT, int NC>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_r_gather_nc(
+    int64_t n, int64_t nl, T *__restrict__ z, const T *__restrict__ wl,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ pos,
+    const T *__restrict__ dinv, double *__restrict__ part, const DevScalars *__restrict__ sc,
+    int check) {
+  if (check && sc->done) return;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  double acc[2 * NC];
+#pragma unroll
+  for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
+  if (v < n) {
+    const int32_t k0 = off[v], k1 = off[v + 1], last = (int32_t)(nl - 1);
+    const T di = ld_v<NT>(dinv + v);
+    T zo[NC], wv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) zo[c] = ld_v<NT>(z + c * n + v);
+    int32_t ps[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) ps[m] = pos[min(k0 + m, last)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T *wc = wl + c * nl;
+      T cm[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) cm[m] = wc[ps[m]];
+      T a = T(0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) a += k0 + m < k1 ? cm[m] : T(0);
+      wv[c] = a;
+    }
+    for (int32_t k = k0 + 4; k < k1; ++k) {
+      const int32_t q = pos[k];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) wv[c] += wl[c * nl + q];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T zv = zo[c] - ((T)sc->alpha[c] * di) * wv[c];
+      st_v<NT>(z + c * n + v, zv);
+      const T rv = di != T(0) ? zv / di : T(0);
+      acc[c] = (double)rv * (double)zv;
+      acc[NC + c] = (double)rv * (double)rv;
+    }
+  }
+  block_partials<2 * NC>(acc, part);
+}
+
 // w[c][v] += Q^T w_L at node v (fixed order as above), one node per thread
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_gather_local(
@@ -896,9 +1004,37 @@ void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStr
   launch_fin(FinKind::Alpha, nc, src, rows, sc, s, check ? 1 : 0);
 }
 
+template <typename T, bool NT, int NC>
+static void launch_update_r_nc(int64_t n, T *r, T *w, const T *dinv, double *part,
+                               DevScalars *sc, hipStream_t s, int check, int64_t n_own) {
+  hipLaunchKernelGGL((k_cg_update_r_nc<T, NT, NC>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, s,
+                     n, r, w, dinv, part, sc, check, n_own);
+}
+
+template <typename T, bool NT>
+static void update_r_nc(int nc, int64_t n, T *r, T *w, const T *dinv, double *part,
+                        DevScalars *sc, hipStream_t s, int check, int64_t n_own) {
+  switch (nc) {
+    case 2: launch_update_r_nc<T, NT, 2>(n, r, w, dinv, part, sc, s, check, n_own); break;
+    case 3: launch_update_r_nc<T, NT, 3>(n, r, w, dinv, part, sc, s, check, n_own); break;
+    case 4: launch_update_r_nc<T, NT, 4>(n, r, w, dinv, part, sc, s, check, n_own); break;
+    case 5: launch_update_r_nc<T, NT, 5>(n, r, w, dinv, part, sc, s, check, n_own); break;
+    case 6: launch_update_r_nc<T, NT, 6>(n, r, w, dinv, part, sc, s, check, n_own); break;
+    case 7: launch_update_r_nc<T, NT, 7>(n, r, w, dinv, part, sc, s, check, n_own); break;
+    default: launch_update_r_nc<T, NT, kMaxComp>(n, r, w, dinv, part, sc, s, check, n_own);
+  }
+}
+
 template <typename T>
 void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, DevScalars *sc,
                  hipStream_t s, bool check, int64_t n_own) {
+  if (nc > 1) {  // one thread per node for every component: dinv read once
+    if (n * (int64_t)sizeof(T) >= kStreamBytes)
+      update_r_nc<T, true>(nc, n, r, w, dinv, part, sc, s, check ? 1 : 0, n_own);
+    else
+      update_r_nc<T, false>(nc, n, r, w, dinv, part, sc, s, check ? 1 : 0, n_own);
+    return;
+  }
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
     hipLaunchKernelGGL((k_cg_update_r<T, true>), dim3(vec_blocks(n), nc),
                        dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0,
@@ -935,10 +1071,41 @@ void gather_local(int nc, int64_t n, int64_t nl, const int32_t *off, const int32
                      off, pos, wl, w, done);
 }
 
+template <typename T, bool NT, int NC>
+static void launch_gather_nc(int64_t n, int64_t nl, T *r, const T *wl, const int32_t *off,
+                             const int32_t *pos, const T *dinv, double *part, DevScalars *sc,
+                             hipStream_t s, int check) {
+  hipLaunchKernelGGL((k_cg_update_r_gather_nc<T, NT, NC>), dim3(vec_blocks(n)),
+                     dim3(kVecThreads), 0, s, n, nl, r, wl, off, pos, dinv, part, sc, check);
+}
+
+template <typename T, bool NT>
+static void update_r_gather_nc(int nc, int64_t n, int64_t nl, T *r, const T *wl,
+                               const int32_t *off, const int32_t *pos, const T *dinv,
+                               double *part, DevScalars *sc, hipStream_t s, int check) {
+  switch (nc) {
+    case 2: launch_gather_nc<T, NT, 2>(n, nl, r, wl, off, pos, dinv, part, sc, s, check); break;
+    case 3: launch_gather_nc<T, NT, 3>(n, nl, r, wl, off, pos, dinv, part, sc, s, check); break;
+    case 4: launch_gather_nc<T, NT, 4>(n, nl, r, wl, off, pos, dinv, part, sc, s, check); break;
+    case 5: launch_gather_nc<T, NT, 5>(n, nl, r, wl, off, pos, dinv, part, sc, s, check); break;
+    case 6: launch_gather_nc<T, NT, 6>(n, nl, r, wl, off, pos, dinv, part, sc, s, check); break;
+    case 7: launch_gather_nc<T, NT, 7>(n, nl, r, wl, off, pos, dinv, part, sc, s, check); break;
+    default:
+      launch_gather_nc<T, NT, kMaxComp>(n, nl, r, wl, off, pos, dinv, part, sc, s, check);
+  }
+}
+
 template <typename T>
 void cg_update_r_gather(int nc, int64_t n, int64_t nl, T *r, const T *wl, const int32_t *off,
                         const int32_t *pos, const T *dinv, double *part, DevScalars *sc,
                         hipStream_t s, bool check) {
+  if (nc > 1) {  // one thread per node for every component: map and dinv read once
+    if (n * (int64_t)sizeof(T) >= kStreamBytes)
+      update_r_gather_nc<T, true>(nc, n, nl, r, wl, off, pos, dinv, part, sc, s, check ? 1 : 0);
+    else
+      update_r_gather_nc<T, false>(nc, n, nl, r, wl, off, pos, dinv, part, sc, s, check ? 1 : 0);
+    return;
+  }
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
     hipLaunchKernelGGL((k_cg_update_r_gather<T, true>), dim3(vec_blocks(n), nc),
                        dim3(kGroupThreads<T>), 0, s, n, nl, r, wl, off, pos, dinv, part, sc,

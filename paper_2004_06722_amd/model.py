@@ -71,9 +71,11 @@ def iteration_bytes(bp: int, p: int, E: int, ncomp: int = 1, word: int = 8,
     library's internal node order (the default) the residual update does not
     clear w on the (p-1)^3 element-interior nodes of each element, which the
     operator overwrites with plain stores: one word less there. The Gauss-
-    Legendre mass (BP1/BP2) assembles by a gather and has no w to clear."""
+    Legendre mass (BP1/BP2) assembles by a gather and has no w to clear. The
+    inverse diagonal is read once per node for all components."""
     n = p ** 3 * E
-    b = apply_bytes(bp, p, E, ncomp, word) + word * VECTOR_WORDS_CG * n * ncomp
+    # dinv (one of the ten words) is shared by the components
+    b = apply_bytes(bp, p, E, ncomp, word) + word * ((VECTOR_WORDS_CG - 1) * ncomp + 1) * n
     if interior_order and bp >= 3:
         b -= word * max(p - 1, 0) ** 3 * E * ncomp
     return b

@@ -64,3 +64,11 @@ def test_interpolate_first_relative_work_matches_the_paper(row):
     p1, g = row["p1_large"], row["gamma"]
     change = model.work_interpolate_first(p1, g) / model.work_direct(p1, g) - 1.0
     assert abs(change - row["relative_change"]) <= row["tolerance"], change
+
+
+def test_vector_iteration_counts_dinv_once():
+    # three components share the map, G and the inverse diagonal: nine vector
+    # words per component and DOF plus one for dinv
+    E, n = 1, 343
+    assert model.iteration_bytes(6, 7, E, 3, interior_order=False) == \
+        model.apply_bytes(6, 7, E, 3) + 8 * (9 * 3 + 1) * n
