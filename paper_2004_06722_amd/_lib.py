@@ -19,6 +19,7 @@ BP_OPT_TIME_APPLY = 1
 BP_OPT_MIXED_MODE = 2
 BP_MIXED_RESTART, BP_MIXED_RELIABLE = 0, 1
 BP_OPT_CG_VARIANT = 3
+BP_OPT_CG_FUSE = 5
 BP_CG_STANDARD, BP_CG_SINGLE_REDUCTION = 0, 1
 BP_STATIC_WS_MB = 64
 

@@ -57,6 +57,9 @@ constexpr int kMaxTimedApplies = 4096;
 struct DevScalars {
   double rz[kMaxComp], pap[kMaxComp], rr[kMaxComp], bb[kMaxComp];
   double rzp[kMaxComp];  // r.z before the last update (used after a residual replacement)
+  // r.z by iteration parity for the fused small-mesh iteration: iteration k
+  // reads rzs[k & 1] and its direction update writes rzs[(k + 1) & 1]
+  double rzs[2][kMaxComp];
   double alpha[kMaxComp], beta[kMaxComp];
   double tol2;
   int done;       // set when every component meets the tolerance
@@ -101,6 +104,7 @@ struct bp_op_s {
   bool time_apply = false;
   int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
   int cg_variant = 0;  // BP_CG_STANDARD or BP_CG_SINGLE_REDUCTION (bp_pcg_solve)
+  bool cg_fuse = true; // BP_OPT_CG_FUSE: the fused iteration on small meshes
   double *sv = nullptr;  // s = A p of the single-reduction PCG (allocated when selected)
   // Gauss-Legendre operators: the gather map transposed (CSR over global
   // nodes: the element-local slots e p1^3 + l of node g are

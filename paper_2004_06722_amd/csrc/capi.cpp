@@ -309,6 +309,12 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
   const int64_t nl = op->nelem * op->p1 * op->p1 * op->p1;
   const T *wl = reinterpret_cast<const T *>(sizeof(T) == 4 ? (const void *)op->wl32
                                                            : (const void *)op->wl);
+  // small meshes (FP64): alpha and beta computed inside the two vector
+  // updates, three launches per iteration; the operator's partials stay at
+  // the start of `part`, the residual update's follow them
+  const bool fused =
+      op->cg_fuse && sizeof(T) == 8 && !mass_wl && !resume && cg_fused_fits(n, nb_apply);
+  double *const part_r = part + nb_apply * nc;
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
     for (int c = 0; c < chunk; ++c) {
@@ -318,6 +324,15 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
                    : launch_apply(op, which, f32, p, w, masked, part, done, s);
       if (rc) return rc;
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
+      if constexpr (sizeof(T) == 8) {
+        if (fused) {
+          const int parity = (it + c) & 1;
+          cg_update_r_fused(nc, n, r, w, dinv, part, nb_apply, part_r, sc, parity, s, check,
+                            stored_rows(op, which));
+          cg_update_xp_fused(nc, n, x, p, r, part_r, sc, parity, s, check);
+          continue;
+        }
+      }
       cg_fin_alpha(nc, part, nb_apply, sc, s, check);
       if (mass_wl)
         cg_update_r_gather<T>(nc, n, nl, r, wl, op->tr_off, op->tr_pos, dinv, part, sc, s,
@@ -1083,6 +1098,11 @@ int bp_set_option(bp_op op, int option, int value) {
       if (rc) return rc;
     }
     op->cg_variant = value;
+    return BP_OK;
+  }
+  if (option == BP_OPT_CG_FUSE) {
+    if (value != 0 && value != 1) return set_error(BP_ERR_ARG, "bp_set_option: CG fuse 0 or 1");
+    op->cg_fuse = value != 0;
     return BP_OK;
   }
   if (option == BP_OPT_MIXED_MODE) {

@@ -80,6 +80,21 @@ template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
                   bool check = true);
 
+// The fused iteration of small meshes (FP64): at most kFusedRows partial
+// rows in both tables. The residual update computes alpha itself from the
+// operator's partials pa[nba][nc] and writes its own partials into pr
+// ([vec_blocks(n)][2 nc]); the direction update computes beta and the
+// convergence test from pr. Three launches per iteration instead of five;
+// parity = iteration index & 1 (selects the r.z slot, DevScalars::rzs).
+constexpr int64_t kFusedRows = 1024;
+bool cg_fused_fits(int64_t n, int64_t nb_apply);
+void cg_update_r_fused(int nc, int64_t n, double *z, double *w, const double *dinv,
+                       const double *pa, int64_t nba, double *pr, DevScalars *sc, int parity,
+                       hipStream_t s, bool check, int64_t n_own);
+void cg_update_xp_fused(int nc, int64_t n, double *x, double *p, const double *z,
+                        const double *pr, DevScalars *sc, int parity, hipStream_t s,
+                        bool check);
+
 // transposed gather Q^T w_L: w[c][g] += sum of wl[c][pos[k]] for k in
 // [off[g], off[g+1]) in ascending order (wl is [nc][nl]); skipped while
 // *done (done may be NULL)

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_init(const double *__restri
   if (threadIdx.x == 0) {
     int bad = 0;
     for (int c = 0; c < nc; ++c) {
-      sc->rz[c] = res[c];
+      sc->rz[c] = sc->rzs[0][c] = res[c];
       sc->rr[c] = res[nc + c];
       sc->bb[c] = res[2 * nc + c];
       sc->alpha[c] = sc->beta[c] = 0.0;
@@ -485,6 +485,163 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_r_gather_nc(
     }
   }
   block_partials<2 * NC>(acc, part);
+}
+
+// ---- the fused iteration of small meshes ----------------------------------
+// With few partial rows every work-group of the residual update reduces the
+// operator's partials itself, and every work-group of the direction update
+// those of the residual update: each in the same fixed order (thread t adds
+// rows t, t + 256, ...; a fixed shuffle tree per wave; the wave sums in
+// order), so all work-groups hold bit-identical alpha and beta and the two
+// single-work-group finishers of the standard iteration are not launched.
+// Only work-group 0 writes the device scalars; nothing in a kernel reads a
+// scalar that the same kernel writes (r.z by iteration parity: rzs).
+template <int W>
+__device__ __forceinline__ void block_reduce_rows(const double *__restrict__ part, int64_t nb,
+                                                  double *res) {
+  constexpr int NW = kVecThreads / 64;
+  __shared__ double red[NW][W];
+  double acc[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) acc[c] = 0.0;
+  for (int64_t r = threadIdx.x; r < nb; r += kVecThreads)
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] += part[r * W + c];
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    double x = acc[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < W) {
+    double x = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) x += red[k][threadIdx.x];
+    res[threadIdx.x] = x;
+  }
+  __syncthreads();
+}
+
+// z -= alpha dinv w for every component (one thread per node), alpha from
+// the operator's partials pa[nba][NC] and r.z of this iteration (rz_old);
+// partials of the new r.z and r.r into pr. A breakdown (see k_fin_alpha) or
+// a non-finite p.Ap leaves z as it is in every work-group and, with a
+// stopping test, ends the solve.
+template <int NC>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_r_fused(
+    int64_t n, double *__restrict__ z, double *__restrict__ w, const double *__restrict__ dinv,
+    const double *__restrict__ pa, int64_t nba, double *__restrict__ pr, DevScalars *sc,
+    int parity, int check, int64_t n_own) {
+  if (check && sc->done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->halted = 1;
+    return;
+  }
+  // the node's vectors are requested first, so that they arrive while the
+  // partial rows are reduced
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const bool in = v < n;
+  double di = 0.0, zo[NC], wo[NC];
+  if (in) {
+    di = dinv[v];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      zo[c] = z[c * n + v];
+      wo[c] = w[c * n + v];
+    }
+  }
+  __shared__ double pap[NC];
+  block_reduce_rows<NC>(pa, nba, pap);
+  double al[NC];
+  int bad = 0, brk = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double rz = sc->rzs[parity][c];
+    al[c] = pap[c] != 0.0 ? rz / pap[c] : 0.0;
+    brk |= indefinite(rz, pap[c]);
+    bad |= !isfinite(pap[c]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int c = 0; c < NC; ++c) {
+      sc->pap[c] = pap[c];
+      sc->alpha[c] = al[c];
+    }
+    if (brk) sc->breakdown = 1;
+    if (bad) sc->nonfinite = 1;
+    if (check && (brk || bad)) sc->done = sc->halted = 1;
+  }
+  if (check && (brk || bad)) return;
+  double acc[2 * NC];
+#pragma unroll
+  for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
+  if (in) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double zv = zo[c] - (al[c] * di) * wo[c];
+      z[c * n + v] = zv;
+      if (v >= n_own) w[c * n + v] = 0.0;
+      const double rv = di != 0.0 ? zv / di : 0.0;
+      acc[c] = rv * zv;
+      acc[NC + c] = rv * rv;
+    }
+  }
+  block_partials<2 * NC>(acc, pr);
+}
+
+// x += alpha p, then p = z + beta p unless the iteration converged; beta and
+// the convergence test from the residual update's partials pr[nbv][2 NC] and
+// r.z of this iteration; work-group 0 stores the new r.z into the other
+// parity slot and updates the scalars the host polls.
+template <int NC>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_xp_fused(
+    int64_t n, double *__restrict__ x, double *__restrict__ p, const double *__restrict__ z,
+    const double *__restrict__ pr, int64_t nbv, DevScalars *sc, int parity, int check) {
+  if (check && sc->halted) return;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const bool in = v < n;
+  double pv[NC], xv[NC], zv[NC];
+  if (in) {  // requested before the reduction, as in the residual update
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      pv[c] = p[c * n + v];
+      xv[c] = x[c * n + v];
+      zv[c] = z[c * n + v];
+    }
+  }
+  __shared__ double res[2 * NC];
+  block_reduce_rows<2 * NC>(pr, nbv, res);
+  double al[NC], be[NC];
+  bool conv = !sc->fixed;
+  int bad = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double rzo = sc->rzs[parity][c], rzn = res[c], rr = res[NC + c];
+    al[c] = sc->alpha[c];
+    be[c] = rzo != 0.0 ? rzn / rzo : 0.0;
+    const double bb = sc->bb[c] > 0.0 ? sc->bb[c] : 1.0;
+    conv = conv && rr <= sc->tol2 * bb;
+    bad |= !isfinite(rzn) || !isfinite(rr);
+  }
+  const bool dir = !(conv || bad);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int c = 0; c < NC; ++c) {
+      sc->rzs[parity ^ 1][c] = res[c];
+      sc->rzp[c] = sc->rzs[parity][c];
+      sc->rz[c] = res[c];
+      sc->rr[c] = res[NC + c];
+      sc->beta[c] = be[c];
+    }
+    sc->iters += 1;
+    if (bad) sc->nonfinite = 1;
+    if (!dir) sc->done = 1;
+  }
+  if (!in) return;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    x[c * n + v] = xv[c] + al[c] * pv[c];
+    if (dir) p[c * n + v] = zv[c] + be[c] * pv[c];
+  }
 }
 
 // w[c][v] += Q^T w_L at node v (fixed order as above), one node per thread
@@ -1051,6 +1208,56 @@ void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStre
   const double *src =
       reduce_stage1(part, nb, 2 * nc, const_cast<double *>(part) + nb * 2 * nc, &rows, s);
   launch_fin(FinKind::Beta, nc, src, rows, sc, s, check ? 1 : 0);
+}
+
+template <int NC>
+static void launch_fused_nc(bool residual, int64_t n, double *x, double *p, double *z,
+                            double *w, const double *dinv, const double *pa, int64_t nba,
+                            double *pr, DevScalars *sc, int parity, int check, int64_t n_own,
+                            hipStream_t s) {
+  if (residual)
+    hipLaunchKernelGGL((k_cg_update_r_fused<NC>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, s,
+                       n, z, w, dinv, pa, nba, pr, sc, parity, check, n_own);
+  else
+    hipLaunchKernelGGL((k_cg_update_xp_fused<NC>), dim3(vec_blocks(n)), dim3(kVecThreads), 0,
+                       s, n, x, p, z, pr, vec_blocks(n), sc, parity, check);
+}
+
+static void launch_fused(bool residual, int nc, int64_t n, double *x, double *p, double *z,
+                         double *w, const double *dinv, const double *pa, int64_t nba,
+                         double *pr, DevScalars *sc, int parity, int check, int64_t n_own,
+                         hipStream_t s) {
+#define BP_FUSED(NC) \
+  launch_fused_nc<NC>(residual, n, x, p, z, w, dinv, pa, nba, pr, sc, parity, check, n_own, s)
+  switch (nc) {
+    case 1: BP_FUSED(1); break;
+    case 2: BP_FUSED(2); break;
+    case 3: BP_FUSED(3); break;
+    case 4: BP_FUSED(4); break;
+    case 5: BP_FUSED(5); break;
+    case 6: BP_FUSED(6); break;
+    case 7: BP_FUSED(7); break;
+    default: BP_FUSED(kMaxComp); break;
+  }
+#undef BP_FUSED
+}
+
+bool cg_fused_fits(int64_t n, int64_t nb_apply) {
+  return vec_blocks(n) <= kFusedRows && nb_apply <= kFusedRows;
+}
+
+void cg_update_r_fused(int nc, int64_t n, double *z, double *w, const double *dinv,
+                       const double *pa, int64_t nba, double *pr, DevScalars *sc, int parity,
+                       hipStream_t s, bool check, int64_t n_own) {
+  launch_fused(true, nc, n, nullptr, nullptr, z, w, dinv, pa, nba, pr, sc, parity,
+               check ? 1 : 0, n_own, s);
+}
+
+void cg_update_xp_fused(int nc, int64_t n, double *x, double *p, const double *z,
+                        const double *pr, DevScalars *sc, int parity, hipStream_t s,
+                        bool check) {
+  launch_fused(false, nc, n, x, p, const_cast<double *>(z), nullptr, nullptr, nullptr, 0,
+               const_cast<double *>(pr), sc, parity, check ? 1 : 0, 0, s);
 }
 
 template <typename T>

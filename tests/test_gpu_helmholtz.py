@@ -123,8 +123,8 @@ def test_helmholtz_without_dirichlet_converges():
         c.close()
 
 
-@pytest.mark.parametrize("sr", [False, True])
-def test_indefinite_operator_reports_breakdown(sr):
+@pytest.mark.parametrize("sr,fuse", [(False, True), (False, False), (True, True)])
+def test_indefinite_operator_reports_breakdown(sr, fuse):
     # H = A + beta B with beta = -300 is indefinite on this mesh (the smooth
     # modes have generalised eigenvalues near 3 pi^2 < 300) while diag(H)
     # stays positive, and for the smooth rhs M f the first step has r.z > 0
@@ -147,6 +147,7 @@ def test_indefinite_operator_reports_breakdown(sr):
         assert hd.diag(HELM)[c.mesh.boundary == 0].min() > 0
         assert bh @ z > 0 and z @ hd.apply(HELM, z) < 0
         c.op.set_cg_variant(sr)
+        c.op.set_option(_lib.BP_OPT_CG_FUSE, 1 if fuse else 0)
         c.op.set_helmholtz(beta)
         b = dev(bh)
         x = torch.zeros_like(b)

@@ -142,13 +142,17 @@ def manufactured_rhs(c):
     return c.disc.apply(MASS, f, masked=False) * c.disc.mask
 
 
+@pytest.mark.parametrize("fuse", [True, False])
 @pytest.mark.parametrize("bp,p,ncomp", [(5, 2, 1), (5, 4, 1), (5, 5, 1), (5, 6, 2), (5, 7, 1),
                                          (5, 5, 8), (3, 4, 1), (3, 6, 1), (1, 5, 1)])
-def test_pcg_iterates_match_oracle_orders(bp, p, ncomp):
+def test_pcg_iterates_match_oracle_orders(bp, p, ncomp, fuse):
     # every order's thread plane (including planes that leave idle lanes in a
-    # wave) and several components: the fused energy p.Ap drives alpha
+    # wave) and several components: the fused energy p.Ap drives alpha; with
+    # fuse the vector updates compute alpha and beta themselves (small meshes)
+    from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
     c = Case(bp, p, *grid_for(p), seed=21, ncomp=ncomp)
     try:
+        c.op.set_option(BP_OPT_CG_FUSE, 1 if fuse else 0)
         which = MASS if bp == 1 else STIFF
         mask = (1 - c.mesh.boundary) if bp >= 3 else np.ones(c.disc.nglobal)
         b = c.vec(3) * (mask[:, None] if ncomp > 1 else mask)
@@ -233,10 +237,13 @@ def test_pcg_iterates_match_oracle_config1():
         c.close()
 
 
-def test_pcg_converged_solution_config1():
+@pytest.mark.parametrize("fuse", [True, False])
+def test_pcg_converged_solution_config1(fuse):
     import scipy.sparse.linalg as spla
+    from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
     c = Case(5, 3, 4, 4, 4, seed=0)
     try:
+        c.op.set_option(BP_OPT_CG_FUSE, 1 if fuse else 0)
         b = manufactured_rhs(c)
         x, st = c.op.pcg_solve(dev(b), rtol=1e-14, maxit=5000)
         assert st["converged"] and st["rel_res"][0] <= 1e-14
