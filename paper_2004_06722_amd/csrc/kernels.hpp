@@ -945,7 +945,13 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nelem, int p1, int q, int 
 
 // ---------------------------------------------------------------------------
 // Gradient with respect to the coefficient at the quadrature points
-// (collocated GLL): g_q = - sum_c (D lam_c)_q^T G_q (D u_c)_q.
+// (collocated GLL): g_q = - sum_c (D lam_c)_q^T G_q (D u_c)_q. The thread
+// layout is that of the stiffness kernel: each lane owns an (i, j) column of
+// an element and requests its G column and map once. Per component it takes
+// the gradient of u (t in registers, r and s through one LDS tile) and forms
+// v = G (D u) at its points, then the gradient of lam through the same tile
+// and accumulates (D lam) . v, so only v, not both gradients, stays live.
+// lam and u are masked on Dirichlet nodes (those read as 0).
 // ---------------------------------------------------------------------------
 template <int P1>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
@@ -953,10 +959,8 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
     const double *__restrict__ basis, const double *__restrict__ lam,
     const double *__restrict__ u, double *__restrict__ gout, int64_t cstride, int ncomp) {
   using PL = Plane<P1, P1>;
-  constexpr int N3 = P1 * P1 * P1, PAD = P1 + 1;
-  __shared__ double sD[P1][P1];
-  __shared__ double sl[PL::EPB][P1][P1][PAD];
-  __shared__ double su[PL::EPB][P1][P1][PAD];
+  constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
+  const double *__restrict__ Dg = basis + PP;  // D^[a][m] at a * p1 + m
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
   const int slot = act ? t / PL::N : 0;
@@ -964,52 +968,69 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
   const int i = ij % P1, j = ij / P1;
   const int64_t e = (int64_t)blockIdx.x * PL::EPB + slot;
   const bool live = act && e < nelem;
-  for (int x = t; x < P1 * P1; x += PL::THREADS) sD[x / P1][x % P1] = basis[P1 * P1 + x];
+  const int64_t ec = live ? e : nelem - 1;  // element whose data the lane reads
+  __shared__ double sD[P1][PAD];
+  __shared__ double sx[PL::EPB][P1][P1][PAD];
+  for (int x = t; x < PP; x += PL::THREADS) sD[x / P1][x % P1] = Dg[x];
   int gk[P1];
+  double g[6][P1];
+  unsigned mb = 0;  // bit k: node k is read (live and not a Dirichlet node)
 #pragma unroll
   for (int k = 0; k < P1; ++k) {
-    const int v = live ? idx[e * N3 + i + P1 * (j + P1 * k)] : -1;
-    gk[k] = decode_index(v, live, 1);
+    const int v = idx[ec * N3 + ij + k * PP];
+    if (live && v >= 0) mb |= 1u << k;
+    gk[k] = v >= 0 ? v : -1 - v;
   }
+#pragma unroll
+  for (int k = 0; k < P1; ++k)
+#pragma unroll
+    for (int n = 0; n < 6; ++n) g[n][k] = G[ec * 6 * N3 + n * N3 + k * PP + ij];
   double acc[P1];
 #pragma unroll
   for (int k = 0; k < P1; ++k) acc[k] = 0.0;
+#pragma unroll 1
   for (int c = 0; c < ncomp; ++c) {
-    double rl[P1], rv[P1];
+    double vr[P1], vs[P1], vt[P1];
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      const double *x = (pass == 0 ? u : lam) + c * cstride;
+      double r[P1], rt[P1];
 #pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      rl[k] = gk[k] >= 0 ? lam[gk[k] + c * cstride] : 0.0;
-      rv[k] = gk[k] >= 0 ? u[gk[k] + c * cstride] : 0.0;
-      if (act) {
-        sl[slot][k][j][i] = rl[k];
-        su[slot][k][j][i] = rv[k];
+      for (int k = 0; k < P1; ++k) {
+        const double val = x[gk[k]];
+        r[k] = (mb >> k & 1u) ? val : 0.0;
+      }
+      __syncthreads();  // the tile's previous contents have been read
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        if (act) sx[slot][k][j][i] = r[k];
+        double a = 0.0;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) a += Dg[k * P1 + m] * r[m];
+        rt[k] = a;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < P1; ++k) {
+        double dr = 0.0, ds = 0.0;
+#pragma unroll
+        for (int m = 0; m < P1; ++m) {
+          dr += sD[i][m] * sx[slot][k][j][m];
+          ds += sD[j][m] * sx[slot][k][m][i];
+        }
+        if (pass == 0) {
+          vr[k] = g[0][k] * dr + g[1][k] * ds + g[2][k] * rt[k];
+          vs[k] = g[1][k] * dr + g[3][k] * ds + g[4][k] * rt[k];
+          vt[k] = g[2][k] * dr + g[4][k] * ds + g[5][k] * rt[k];
+        } else {
+          acc[k] += dr * vr[k] + ds * vs[k] + rt[k] * vt[k];
+        }
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      double lr = 0, ls = 0, lt = 0, ur = 0, us = 0, ut = 0;
-#pragma unroll
-      for (int m = 0; m < P1; ++m) {
-        lr += sD[i][m] * sl[slot][k][j][m];
-        ls += sD[j][m] * sl[slot][k][m][i];
-        lt += sD[k][m] * rl[m];
-        ur += sD[i][m] * su[slot][k][j][m];
-        us += sD[j][m] * su[slot][k][m][i];
-        ut += sD[k][m] * rv[m];
-      }
-      const double *Gq = G + (live ? e : 0) * 6 * N3 + k * P1 * P1 + ij;
-      double g[6];
-#pragma unroll
-      for (int n = 0; n < 6; ++n) g[n] = live ? Gq[n * N3] : 0.0;
-      acc[k] += lr * (g[0] * ur + g[1] * us + g[2] * ut) + ls * (g[1] * ur + g[3] * us + g[4] * ut) +
-                lt * (g[2] * ur + g[4] * us + g[5] * ut);
-    }
-    __syncthreads();
   }
   if (live)
 #pragma unroll
-    for (int k = 0; k < P1; ++k) gout[e * N3 + k * P1 * P1 + ij] = -acc[k];
+    for (int k = 0; k < P1; ++k) gout[e * N3 + k * PP + ij] = -acc[k];
 }
 
 }  // namespace bp
