@@ -1,6 +1,7 @@
 // Internal declarations of the bake-off library (host side).
 #pragma once
 
+#include "rules1d.hpp"
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -22,13 +23,7 @@ int set_error(int code, const std::string &msg);
   } while (0)
 
 // ---- host setup (setup.cpp) ----------------------------------------------
-// 1D rules on [-1, 1], ascending.
-void gll_rule(int n, double *x, double *w);
-void gl_rule(int n, double *x, double *w);
-// Lagrange basis on `nodes` (n) evaluated / differentiated at `pts` (m):
-// out[a*n + j] = h_j(pts[a]) or h_j'(pts[a]) (barycentric form).
-void lagrange_interp(int n, const double *nodes, int m, const double *pts, double *out);
-void lagrange_deriv(int n, const double *nodes, int m, const double *pts, double *out);
+// 1D rules on [-1, 1], ascending, and the Lagrange matrices: rules1d.hpp.
 
 // Per-operator 1D data: nodes, quadrature, J (q x p1), D (q x p1), Dq (q x q).
 struct Basis {

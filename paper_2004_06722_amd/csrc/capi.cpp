@@ -103,20 +103,12 @@ void release(bp_op op) {
   delete op;
 }
 
-// Even-odd tables of the q x p1 matrix M with M[q-1-a][p1-1-i] = sign M[a][i]
-// (symmetric point sets): for a < (q+1)/2, (M[a][i] + M[a][p1-1-i]) / 2 and
-// (M[a][i] - M[a][p1-1-i]) / 2 for i < p1/2, then M[a][p1/2] for odd p1. M is
-// first symmetrised, so that entries zero by symmetry are exactly zero.
-void even_odd_table(const std::vector<double> &M, int q, int p1, int sign,
-                    std::vector<double> &out) {
-  auto ms = [&](int a, int i) {
-    return 0.5 * (M[(size_t)a * p1 + i] + sign * M[(size_t)(q - 1 - a) * p1 + (p1 - 1 - i)]);
-  };
-  for (int a = 0; a < (q + 1) / 2; ++a) {
-    for (int i = 0; i < p1 / 2; ++i) out.push_back(0.5 * (ms(a, i) + ms(a, p1 - 1 - i)));
-    for (int i = 0; i < p1 / 2; ++i) out.push_back(0.5 * (ms(a, i) - ms(a, p1 - 1 - i)));
-    if (p1 & 1) out.push_back(ms(a, p1 / 2));
-  }
+// Appends the even-odd table (rules1d.hpp) of the q x p1 matrix M.
+void append_even_odd(const std::vector<double> &M, int q, int p1, int sign,
+                     std::vector<double> &out) {
+  const size_t o = out.size();
+  out.resize(o + (size_t)((q + 1) / 2) * p1);
+  even_odd_table(M.data(), q, p1, sign, out.data() + o);
 }
 
 // Upload basis J | D | Dq | 1D quadrature weights | even-odd tables of J and D
@@ -128,8 +120,8 @@ int upload_basis(bp_op op, hipStream_t s) {
   all.insert(all.end(), b.D.begin(), b.D.end());
   all.insert(all.end(), b.Dq.begin(), b.Dq.end());
   all.insert(all.end(), b.rho.begin(), b.rho.end());
-  even_odd_table(b.J, b.q, b.p1, 1, all);
-  even_odd_table(b.D, b.q, b.p1, -1, all);
+  append_even_odd(b.J, b.q, b.p1, 1, all);
+  append_even_odd(b.D, b.q, b.p1, -1, all);
   int rc = dmalloc(&op->basis_d, all.size());
   if (rc) return rc;
   BP_HIP(hipMemcpyAsync(op->basis_d, all.data(), all.size() * sizeof(double),

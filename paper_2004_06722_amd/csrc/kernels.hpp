@@ -11,6 +11,7 @@
 // sum_e u_L^T w_L (Appendix A1: rho = w^T u before assembly) is reduced per
 // work-group into a partial sum.
 #pragma once
+#include "rules1d.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -98,10 +99,12 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // (energy column c0).
 template <int P1, typename T, bool LOCAL, bool HELM, bool MULTI>
 __device__ __forceinline__ void stiff_colloc_body(
-    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *__restrict__ Dg,
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
     const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int64_t cs, int ncomp,
     int c0, int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
   constexpr int NC = 1;  // LDS tiles of one component at a time
+  static constexpr GLLDeriv<P1, T> kD{};  // D^, compile-time constants
+  const T *const Dg = kD.D;
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
   if (done && *done) return;
@@ -266,9 +269,10 @@ __device__ __forceinline__ void stiff_colloc_body(
 // map at entry, then gathers u, then computes from registers and LDS. The k direction stays in registers; the r and s contractions go
 // through LDS tiles. Loads are branch-free: an element slot past the end
 // reads the last element and a Dirichlet node reads its (valid) global
-// entry, both masked. Entries of D^ with compile-time indices
-// are scalar loads from Dg (global memory, D^[a][m] at a * p1 + m); the
-// lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
+// entry, both masked. D^ is a compile-time table (rules1d.hpp): entries
+// with compile-time indices are immediates, which the compiler rematerialises
+// in each component of the loop instead of keeping them in scalar registers;
+// the lane-dependent rows come from LDS. The local energy u_L^T A_L u_L is
 // accumulated at the quadrature points as (D u)^T G (D u) = u_L^T w_L.
 // HELM adds the Helmholtz term of eq. (hm2): with collocated GLL points the
 // mass matrix is diagonal, so w_L += (beta B~) u_L node by node, with the
@@ -277,19 +281,19 @@ __device__ __forceinline__ void stiff_colloc_body(
 // ---------------------------------------------------------------------------
 template <int P1, typename T, bool LOCAL = false, bool HELM = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
-    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *__restrict__ Dg,
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
     const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
     int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
-  stiff_colloc_body<P1, T, LOCAL, HELM, false>(nelem, idx, G, Dg, Bb, u, w, 0, ncomp, c0, masked,
+  stiff_colloc_body<P1, T, LOCAL, HELM, false>(nelem, idx, G, Bb, u, w, 0, ncomp, c0, masked,
                                                part, done, own);
 }
 
 template <int P1, typename T, bool LOCAL = false, bool HELM = false>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS), 2) void k_stiff_colloc_nc(
-    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G, const T *__restrict__ Dg,
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
     const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int64_t cs,
     int ncomp, int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
-  stiff_colloc_body<P1, T, LOCAL, HELM, true>(nelem, idx, G, Dg, Bb, u, w, cs, ncomp, 0, masked,
+  stiff_colloc_body<P1, T, LOCAL, HELM, true>(nelem, idx, G, Bb, u, w, cs, ncomp, 0, masked,
                                               part, done, own);
 }
 
@@ -492,12 +496,12 @@ struct GLPlane {
   static constexpr int THREADS = ((USED + 63) / 64) * 64;
 };
 
-template <int P1, int Q, typename T, int MODE, bool LOCAL = false, bool WL = false>
-__global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
+template <int P1, int Q, typename T, int MODE, bool LOCAL, bool WL, bool MULTI>
+__device__ __forceinline__ void gl_body(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
     const T *__restrict__ Bb, const T *__restrict__ basis, const T *__restrict__ u,
-    T *__restrict__ w, int ncomp, int c0, int masked, double *__restrict__ part,
-    const int *__restrict__ done, int own) {
+    T *__restrict__ w, int64_t cs, int64_t ws, int ncomp, int c0, int masked,
+    double *__restrict__ part, const int *__restrict__ done, int own) {
   using PL = GLPlane<P1, Q, MODE>;
   using EO = EvenOdd<Q, P1>;
   constexpr bool STIFF = MODE != kGLMass, HELM = MODE == kGLHelm;
@@ -506,6 +510,10 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
   constexpr int LA = Q * P1;                // A tiles: [j][c][i]
   constexpr int RS = PL::RS, LB = Q * RS;   // B tiles: [b][c][i], rows of RS
   static_assert(Q == P1 + 1, "Gauss-Legendre kernel expects q = p1 + 1");
+  // several stiffness components: v at the points goes through the pencil's
+  // own LDS rows (RS >= q entries) instead of three register accumulators
+  // beside G, which stays in registers for all components
+  constexpr bool VST = MULTI && MODE == kGLStiff && RS >= Q;
   if (done && *done) return;
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
@@ -528,8 +536,11 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
   T *const B0 = sB[slot][0];
   T *const B1 = sB[slot][STIFF ? 1 : 0];
   T *const B2 = sB[slot][PL::NB - 1];
-  const T *tJ = basis + 2 * Q * P1 + QQ + Q;  // even-odd tables of J^, then of D^
-  const T *tD = tJ + EO::SIZE;
+  // even-odd tables of J^ and D^, compile-time constants (immediates)
+  static constexpr GLTables<P1, Q, T> kTab{};
+  static_assert(GLTables<P1, Q, T>::SIZE == EO::SIZE, "even-odd table size");
+  const T *tJ = kTab.J;
+  const T *tD = kTab.D;
 
   // one round trip: node column of the gather map, the r-pencil's G / B~
   int gk[P1];
@@ -553,209 +564,280 @@ __global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
     if (!LOCAL) gk[k] = v >= 0 ? v : -1 - v;
   }
 
-  // 1: gather, then along t
-  if (col) {
-    T uk[P1];
+  // components one after the other through the same tiles (MULTI), with G,
+  // the map and the masks kept in registers
+  const int nrun = MULTI ? ncomp : 1;
+  // Several stiffness components (arithmetic and latency bound, not HBM
+  // bound): the next component's column of u is requested during stage 4 of
+  // the current one, so its gather latency overlaps the last two stages.
+  // Lanes without a column read column (0, 0), a valid address.
+  constexpr bool PREF = MULTI && STIFF;
+  T un[PREF ? P1 : 1];
+  if constexpr (PREF)
 #pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      const T v = u[gk[k]];
-      uk[k] = (mb >> k & 1u) ? v : T(0);
-    }
-    const Folded<P1, T> f = fold(uk);
-    T *a0 = A0 + cj * LA + ci;
-    T *a1 = A1 + cj * LA + ci;
+    for (int k = 0; k < P1; ++k) un[k] = u[gk[k]];
+#pragma unroll 1
+  for (int cc = 0; cc < nrun; ++cc) {
+    if (cc > 0) __syncthreads();  // the previous component's A tiles have been read
+    const T *const uc = u + (MULTI ? cc * cs : 0);
+    T *const wc = w + (MULTI ? cc * ws : 0);
+    // 1: gather, then along t
+    if (col) {
+      T uk[P1];
 #pragma unroll
-    for (int c = 0; c < EO::ROWS; ++c) {
-      T ya, yb;
-      eo_row<Q, P1, 1>(tJ, c, f, ya, yb);
-      a0[c * P1] = ya;
-      if (c < EO::HO) a0[(Q - 1 - c) * P1] = yb;
-      if constexpr (STIFF) {
-        eo_row<Q, P1, -1>(tD, c, f, ya, yb);
-        a1[c * P1] = ya;
-        if (c < EO::HO) a1[(Q - 1 - c) * P1] = yb;
+      for (int k = 0; k < P1; ++k) {
+        const T v = PREF ? un[PREF ? k : 0] : uc[gk[k]];
+        uk[k] = (mb >> k & 1u) ? v : T(0);
+      }
+      const Folded<P1, T> f = fold(uk);
+      T *a0 = A0 + cj * LA + ci;
+      T *a1 = A1 + cj * LA + ci;
+#pragma unroll
+      for (int c = 0; c < EO::ROWS; ++c) {
+        T ya, yb;
+        eo_row<Q, P1, 1>(tJ, c, f, ya, yb);
+        a0[c * P1] = ya;
+        if (c < EO::HO) a0[(Q - 1 - c) * P1] = yb;
+        if constexpr (STIFF) {
+          eo_row<Q, P1, -1>(tD, c, f, ya, yb);
+          a1[c * P1] = ya;
+          if (c < EO::HO) a1[(Q - 1 - c) * P1] = yb;
+        }
       }
     }
-  }
-  __syncthreads();
-  // 2: along s (pencil (i, c) = lane l: its column of the A tiles is l + j LA)
-  if (spn) {
-    const int ob = (l / P1) * RS + l % P1;  // (c, i) in the B tiles
-    T x[P1];
+    __syncthreads();
+    // 2: along s (pencil (i, c) = lane l: its column of the A tiles is l + j LA)
+    if (spn) {
+      const int ob = (l / P1) * RS + l % P1;  // (c, i) in the B tiles
+      T x[P1];
 #pragma unroll
-    for (int j = 0; j < P1; ++j) x[j] = A0[j * LA + l];
-    const Folded<P1, T> f = fold(x);
-#pragma unroll
-    for (int b = 0; b < EO::ROWS; ++b) {
-      T ya, yb;
-      eo_row<Q, P1, 1>(tJ, b, f, ya, yb);
-      B0[b * LB + ob] = ya;
-      if (b < EO::HO) B0[(Q - 1 - b) * LB + ob] = yb;
-      if constexpr (STIFF) {
-        eo_row<Q, P1, -1>(tD, b, f, ya, yb);
-        B1[b * LB + ob] = ya;
-        if (b < EO::HO) B1[(Q - 1 - b) * LB + ob] = yb;
-      }
-    }
-    if constexpr (STIFF) {
-#pragma unroll
-      for (int j = 0; j < P1; ++j) x[j] = A1[j * LA + l];
-      const Folded<P1, T> f1 = fold(x);
+      for (int j = 0; j < P1; ++j) x[j] = A0[j * LA + l];
+      const Folded<P1, T> f = fold(x);
 #pragma unroll
       for (int b = 0; b < EO::ROWS; ++b) {
         T ya, yb;
-        eo_row<Q, P1, 1>(tJ, b, f1, ya, yb);
-        B2[b * LB + ob] = ya;
-        if (b < EO::HO) B2[(Q - 1 - b) * LB + ob] = yb;
+        eo_row<Q, P1, 1>(tJ, b, f, ya, yb);
+        B0[b * LB + ob] = ya;
+        if (b < EO::HO) B0[(Q - 1 - b) * LB + ob] = yb;
+        if constexpr (STIFF) {
+          eo_row<Q, P1, -1>(tD, b, f, ya, yb);
+          B1[b * LB + ob] = ya;
+          if (b < EO::HO) B1[(Q - 1 - b) * LB + ob] = yb;
+        }
+      }
+      if constexpr (STIFF) {
+#pragma unroll
+        for (int j = 0; j < P1; ++j) x[j] = A1[j * LA + l];
+        const Folded<P1, T> f1 = fold(x);
+#pragma unroll
+        for (int b = 0; b < EO::ROWS; ++b) {
+          T ya, yb;
+          eo_row<Q, P1, 1>(tJ, b, f1, ya, yb);
+          B2[b * LB + ob] = ya;
+          if (b < EO::HO) B2[(Q - 1 - b) * LB + ob] = yb;
+        }
       }
     }
-  }
-  __syncthreads();
-  // 3: along r, the quadrature points, and back along r
-  double en = 0.0;
-  if (l < QQ) {
-    T y[P1];
+    __syncthreads();
+    // 3: along r, the quadrature points, and back along r
+    double en = 0.0;
+    if (l < QQ) {
+      T y[P1];
 #pragma unroll
-    for (int i = 0; i < P1; ++i) y[i] = B0[rrow + i];
-    const Folded<P1, T> f0 = fold(y);
-    if constexpr (!STIFF) {
-      Unfold<P1, T> z;
-      z.zero();
+      for (int i = 0; i < P1; ++i) y[i] = B0[rrow + i];
+      const Folded<P1, T> f0 = fold(y);
+      if constexpr (!STIFF) {
+        Unfold<P1, T> z;
+        z.zero();
 #pragma unroll
-      for (int a = 0; a < EO::ROWS; ++a) {
-        const bool pair = a < EO::HO;
-        T xa, xb;
-        eo_row<Q, P1, 1>(tJ, a, f0, xa, xb);
-        const T va = g[0][a] * xa;
-        const T vb = pair ? g[0][Q - 1 - a] * xb : T(0);
-        if (live) en += (double)xa * (double)va + (pair ? (double)xb * (double)vb : 0.0);
-        z.template add<Q, 1>(tJ, a, va, vb);
-      }
-      z.get(y);
-#pragma unroll
-      for (int i = 0; i < P1; ++i) B0[rrow + i] = y[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < P1; ++i) y[i] = B1[rrow + i];
-      const Folded<P1, T> f1 = fold(y);
-#pragma unroll
-      for (int i = 0; i < P1; ++i) y[i] = B2[rrow + i];
-      const Folded<P1, T> f2 = fold(y);
-      T bq[HELM ? Q : 1];
-      if constexpr (HELM) {
-        const T *Be = Bb + ec * NQ + rl;
-#pragma unroll
-        for (int a = 0; a < Q; ++a) bq[a] = Be[a * QQ];
-      }
-      Unfold<P1, T> zp, zr, zt;
-      zp.zero();
-      zr.zero();
-      zt.zero();
-#pragma unroll
-      for (int a = 0; a < EO::ROWS; ++a) {
-        const bool pair = a < EO::HO;
-        const int b = Q - 1 - a;
-        T ra, rb, sa, sb, ta, tb;
-        eo_row<Q, P1, -1>(tD, a, f0, ra, rb);
-        eo_row<Q, P1, 1>(tJ, a, f1, sa, sb);
-        eo_row<Q, P1, 1>(tJ, a, f2, ta, tb);
-        const T vra = g[0][a] * ra + g[1][a] * sa + g[2][a] * ta;
-        const T vsa = g[1][a] * ra + g[3][a] * sa + g[4][a] * ta;
-        const T vta = g[2][a] * ra + g[4][a] * sa + g[5][a] * ta;
-        T vrb = 0, vsb = 0, vtb = 0;
-        if (pair) {
-          vrb = g[0][b] * rb + g[1][b] * sb + g[2][b] * tb;
-          vsb = g[1][b] * rb + g[3][b] * sb + g[4][b] * tb;
-          vtb = g[2][b] * rb + g[4][b] * sb + g[5][b] * tb;
-        }
-        if (live) {
-          en += (double)ra * (double)vra + (double)sa * (double)vsa + (double)ta * (double)vta;
-          if (pair)
-            en += (double)rb * (double)vrb + (double)sb * (double)vsb + (double)tb * (double)vtb;
-        }
-        zp.template add<Q, -1>(tD, a, vra, vrb);
-        zr.template add<Q, 1>(tJ, a, vsa, vsb);
-        zt.template add<Q, 1>(tJ, a, vta, vtb);
-        if constexpr (HELM) {
+        for (int a = 0; a < EO::ROWS; ++a) {
+          const bool pair = a < EO::HO;
           T xa, xb;
           eo_row<Q, P1, 1>(tJ, a, f0, xa, xb);
-          const T wa = bq[a] * xa;
-          const T wb = pair ? bq[b] * xb : T(0);
-          if (live) en += (double)xa * (double)wa + (pair ? (double)xb * (double)wb : 0.0);
-          zp.template add<Q, 1>(tJ, a, wa, wb);
+          const T va = g[0][a] * xa;
+          const T vb = pair ? g[0][Q - 1 - a] * xb : T(0);
+          if (live) en += (double)xa * (double)va + (pair ? (double)xb * (double)vb : 0.0);
+          z.template add<Q, 1>(tJ, a, va, vb);
+        }
+        z.get(y);
+#pragma unroll
+        for (int i = 0; i < P1; ++i) B0[rrow + i] = y[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < P1; ++i) y[i] = B1[rrow + i];
+        const Folded<P1, T> f1 = fold(y);
+#pragma unroll
+        for (int i = 0; i < P1; ++i) y[i] = B2[rrow + i];
+        const Folded<P1, T> f2 = fold(y);
+        T bq[HELM ? Q : 1];
+        if constexpr (HELM) {
+          const T *Be = Bb + ec * NQ + rl;
+#pragma unroll
+          for (int a = 0; a < Q; ++a) bq[a] = Be[a * QQ];
+        }
+        Unfold<P1, T> zp, zr, zt;
+        if constexpr (!VST) {
+          zp.zero();
+          zr.zero();
+          zt.zero();
+        }
+#pragma unroll
+        for (int a = 0; a < EO::ROWS; ++a) {
+          const bool pair = a < EO::HO;
+          const int b = Q - 1 - a;
+          T ra, rb, sa, sb, ta, tb;
+          eo_row<Q, P1, -1>(tD, a, f0, ra, rb);
+          eo_row<Q, P1, 1>(tJ, a, f1, sa, sb);
+          eo_row<Q, P1, 1>(tJ, a, f2, ta, tb);
+          const T vra = g[0][a] * ra + g[1][a] * sa + g[2][a] * ta;
+          const T vsa = g[1][a] * ra + g[3][a] * sa + g[4][a] * ta;
+          const T vta = g[2][a] * ra + g[4][a] * sa + g[5][a] * ta;
+          T vrb = 0, vsb = 0, vtb = 0;
+          if (pair) {
+            vrb = g[0][b] * rb + g[1][b] * sb + g[2][b] * tb;
+            vsb = g[1][b] * rb + g[3][b] * sb + g[4][b] * tb;
+            vtb = g[2][b] * rb + g[4][b] * sb + g[5][b] * tb;
+          }
+          if (live) {
+            en += (double)ra * (double)vra + (double)sa * (double)vsa + (double)ta * (double)vta;
+            if (pair)
+              en += (double)rb * (double)vrb + (double)sb * (double)vsb + (double)tb * (double)vtb;
+          }
+          if constexpr (VST) {  // v at the points into the pencil's own rows
+            B0[rrow + a] = vra;
+            B1[rrow + a] = vsa;
+            B2[rrow + a] = vta;
+            if (pair) {
+              B0[rrow + b] = vrb;
+              B1[rrow + b] = vsb;
+              B2[rrow + b] = vtb;
+            }
+          } else {
+            zp.template add<Q, -1>(tD, a, vra, vrb);
+            zr.template add<Q, 1>(tJ, a, vsa, vsb);
+            zt.template add<Q, 1>(tJ, a, vta, vtb);
+          }
+          if constexpr (HELM) {
+            T xa, xb;
+            eo_row<Q, P1, 1>(tJ, a, f0, xa, xb);
+            const T wa = bq[a] * xa;
+            const T wb = pair ? bq[b] * xb : T(0);
+            if (live) en += (double)xa * (double)wa + (pair ? (double)xb * (double)wb : 0.0);
+            zp.template add<Q, 1>(tJ, a, wa, wb);
+          }
+        }
+        if constexpr (VST) {
+          zp.zero();
+          zr.zero();
+          zt.zero();
+#pragma unroll
+          for (int a = 0; a < EO::ROWS; ++a) {
+            const bool pair = a < EO::HO;
+            const int b = Q - 1 - a;
+            zp.template add<Q, -1>(tD, a, B0[rrow + a], pair ? B0[rrow + b] : T(0));
+            zr.template add<Q, 1>(tJ, a, B1[rrow + a], pair ? B1[rrow + b] : T(0));
+            zt.template add<Q, 1>(tJ, a, B2[rrow + a], pair ? B2[rrow + b] : T(0));
+          }
+        }
+        zp.get(y);
+#pragma unroll
+        for (int i = 0; i < P1; ++i) B0[rrow + i] = y[i];
+        zr.get(y);
+#pragma unroll
+        for (int i = 0; i < P1; ++i) B1[rrow + i] = y[i];
+        zt.get(y);
+#pragma unroll
+        for (int i = 0; i < P1; ++i) B2[rrow + i] = y[i];
+      }
+    }
+    __syncthreads();
+    if constexpr (PREF) {  // unconditional (the last component re-reads its own)
+      const T *un_src = u + (cc + 1 < nrun ? cc + 1 : cc) * cs;
+#pragma unroll
+      for (int k = 0; k < P1; ++k) un[k] = un_src[gk[k]];
+    }
+    // 4: back along s (pencil (i, c) = lane l), into the A tiles in place
+    if (spn) {
+      const int ob = (l / P1) * RS + l % P1;
+      Unfold<P1, T> s1, s2;
+      s1.zero();
+      if constexpr (STIFF) s2.zero();
+#pragma unroll
+      for (int b = 0; b < EO::ROWS; ++b) {
+        const bool pair = b < EO::HO;
+        const int bm = (Q - 1 - b) * LB + ob;
+        s1.template add<Q, 1>(tJ, b, B0[b * LB + ob], pair ? B0[bm] : T(0));
+        if constexpr (STIFF) {
+          s1.template add<Q, -1>(tD, b, B1[b * LB + ob], pair ? B1[bm] : T(0));
+          s2.template add<Q, 1>(tJ, b, B2[b * LB + ob], pair ? B2[bm] : T(0));
         }
       }
-      zp.get(y);
+      T z[P1];
+      s1.get(z);
 #pragma unroll
-      for (int i = 0; i < P1; ++i) B0[rrow + i] = y[i];
-      zr.get(y);
-#pragma unroll
-      for (int i = 0; i < P1; ++i) B1[rrow + i] = y[i];
-      zt.get(y);
-#pragma unroll
-      for (int i = 0; i < P1; ++i) B2[rrow + i] = y[i];
-    }
-  }
-  __syncthreads();
-  // 4: back along s (pencil (i, c) = lane l), into the A tiles in place
-  if (spn) {
-    const int ob = (l / P1) * RS + l % P1;
-    Unfold<P1, T> s1, s2;
-    s1.zero();
-    if constexpr (STIFF) s2.zero();
-#pragma unroll
-    for (int b = 0; b < EO::ROWS; ++b) {
-      const bool pair = b < EO::HO;
-      const int bm = (Q - 1 - b) * LB + ob;
-      s1.template add<Q, 1>(tJ, b, B0[b * LB + ob], pair ? B0[bm] : T(0));
+      for (int j = 0; j < P1; ++j) A0[j * LA + l] = z[j];
       if constexpr (STIFF) {
-        s1.template add<Q, -1>(tD, b, B1[b * LB + ob], pair ? B1[bm] : T(0));
-        s2.template add<Q, 1>(tJ, b, B2[b * LB + ob], pair ? B2[bm] : T(0));
+        s2.get(z);
+#pragma unroll
+        for (int j = 0; j < P1; ++j) A1[j * LA + l] = z[j];
       }
     }
-    T z[P1];
-    s1.get(z);
+    __syncthreads();
+    // 5: back along t and scatter
+    if (col) {
+      const T *a0 = A0 + cj * LA + ci;
+      const T *a1 = A1 + cj * LA + ci;
+      Unfold<P1, T> wz;
+      wz.zero();
 #pragma unroll
-    for (int j = 0; j < P1; ++j) A0[j * LA + l] = z[j];
-    if constexpr (STIFF) {
-      s2.get(z);
+      for (int c = 0; c < EO::ROWS; ++c) {
+        const bool pair = c < EO::HO;
+        wz.template add<Q, 1>(tJ, c, a0[c * P1], pair ? a0[(Q - 1 - c) * P1] : T(0));
+        if constexpr (STIFF)
+          wz.template add<Q, -1>(tD, c, a1[c * P1], pair ? a1[(Q - 1 - c) * P1] : T(0));
+      }
+      T wk[P1];
+      wz.get(wk);
 #pragma unroll
-      for (int j = 0; j < P1; ++j) A1[j * LA + l] = z[j];
-    }
-  }
-  __syncthreads();
-  // 5: back along t and scatter
-  if (col) {
-    const T *a0 = A0 + cj * LA + ci;
-    const T *a1 = A1 + cj * LA + ci;
-    Unfold<P1, T> wz;
-    wz.zero();
-#pragma unroll
-    for (int c = 0; c < EO::ROWS; ++c) {
-      const bool pair = c < EO::HO;
-      wz.template add<Q, 1>(tJ, c, a0[c * P1], pair ? a0[(Q - 1 - c) * P1] : T(0));
-      if constexpr (STIFF)
-        wz.template add<Q, -1>(tD, c, a1[c * P1], pair ? a1[(Q - 1 - c) * P1] : T(0));
-    }
-    T wk[P1];
-    wz.get(wk);
-#pragma unroll
-    for (int k = 0; k < P1; ++k) {
-      if constexpr (LOCAL) {  // element-local output, one lane per entry: no assembly
-        if (mb >> k & 1u) w[gk[k]] = wk[k];
-      } else if constexpr (WL) {
-        // w_L of the element (0 at skipped nodes); the caller applies Q^T
-        if (live) w[ec * N3 + ci + P1 * (cj + P1 * k)] = (mb >> k & 1u) ? wk[k] : T(0);
-      } else if (mb >> k & 1u) {
-        if (own && interior_node<P1>(ci, cj, k))
-          w[gk[k]] = wk[k];  // a node of this element alone
-        else
-          atomic_add(w + gk[k], wk[k]);
+      for (int k = 0; k < P1; ++k) {
+        if constexpr (LOCAL) {  // element-local output, one lane per entry: no assembly
+          if (mb >> k & 1u) wc[gk[k]] = wk[k];
+        } else if constexpr (WL) {
+          // w_L of the element (0 at skipped nodes); the caller applies Q^T
+          if (live) wc[ec * N3 + ci + P1 * (cj + P1 * k)] = (mb >> k & 1u) ? wk[k] : T(0);
+        } else if (mb >> k & 1u) {
+          if (own && interior_node<P1>(ci, cj, k))
+            wc[gk[k]] = wk[k];  // a node of this element alone
+          else
+            atomic_add(wc + gk[k], wk[k]);
+        }
       }
     }
+    double enb[1] = {en};
+    if (part)
+      block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + (MULTI ? cc : c0),
+                                      1);
   }
-  double enb[1] = {en};
-  if (part) block_sum_store<1, PL::THREADS>(enb, part + (int64_t)blockIdx.x * ncomp + c0, 1);
+}
+
+template <int P1, int Q, typename T, int MODE, bool LOCAL = false, bool WL = false>
+__global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
+    const T *__restrict__ Bb, const T *__restrict__ basis, const T *__restrict__ u,
+    T *__restrict__ w, int ncomp, int c0, int masked, double *__restrict__ part,
+    const int *__restrict__ done, int own) {
+  gl_body<P1, Q, T, MODE, LOCAL, WL, false>(nelem, idx, Gm, Bb, basis, u, w, 0, 0, ncomp, c0,
+                                            masked, part, done, own);
+}
+
+template <int P1, int Q, typename T, int MODE, bool LOCAL = false, bool WL = false>
+__global__ __launch_bounds__((GLPlane<P1, Q, MODE>::THREADS), 2) void k_op_gl_nc(
+    int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ Gm,
+    const T *__restrict__ Bb, const T *__restrict__ basis, const T *__restrict__ u,
+    T *__restrict__ w, int64_t cs, int64_t ws, int ncomp, int masked, double *__restrict__ part,
+    const int *__restrict__ done, int own) {
+  gl_body<P1, Q, T, MODE, LOCAL, WL, true>(nelem, idx, Gm, Bb, basis, u, w, cs, ws, ncomp, 0,
+                                           masked, part, done, own);
 }
 
 // ---------------------------------------------------------------------------
@@ -956,11 +1038,12 @@ __global__ __launch_bounds__(256) void k_diag(int64_t nelem, int p1, int q, int 
 template <int P1>
 __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_grad_kappa_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const double *__restrict__ G,
-    const double *__restrict__ basis, const double *__restrict__ lam,
-    const double *__restrict__ u, double *__restrict__ gout, int64_t cstride, int ncomp) {
+    const double *__restrict__ lam, const double *__restrict__ u, double *__restrict__ gout,
+    int64_t cstride, int ncomp) {
   using PL = Plane<P1, P1>;
   constexpr int N3 = P1 * P1 * P1, PP = P1 * P1, PAD = P1 + 1;
-  const double *__restrict__ Dg = basis + PP;  // D^[a][m] at a * p1 + m
+  static constexpr GLLDeriv<P1, double> kD{};  // D^[a][m] at a * p1 + m, compile-time
+  const double *const Dg = kD.D;
   const int t = threadIdx.x;
   const bool act = t < PL::USED;
   const int slot = act ? t / PL::N : 0;

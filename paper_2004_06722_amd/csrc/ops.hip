@@ -50,19 +50,18 @@ template <int P1, typename T, bool LOCAL, bool HELM>
 int stiff_colloc(const bp_op_s *op, const T *G, const T *basis, const T *Bb, const T *u, T *w,
                  int masked, double *part, const int *done, hipStream_t s) {
   using PL = Plane<P1, P1>;
-  const T *Dg = basis + P1 * P1;  // D^ follows J^ (both p1 x p1 here)
   const int64_t cs = vec_stride<LOCAL>(op);
   if constexpr (P1 <= (HELM ? 7 : 8)) {
     if (op->ncomp > 1) {
       hipLaunchKernelGGL((k_stiff_colloc_nc<P1, T, LOCAL, HELM>), dim3(apply_blocks(op)),
-                         dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Dg, Bb, u, w, cs,
+                         dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Bb, u, w, cs,
                          op->ncomp, masked, part, done, owned(op));
       return BP_OK;
     }
   }
   for (int c = 0; c < op->ncomp; ++c)
     hipLaunchKernelGGL((k_stiff_colloc<P1, T, LOCAL, HELM>), dim3(apply_blocks(op)),
-                       dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Dg, Bb, u + c * cs,
+                       dim3(PL::THREADS), 0, s, op->nelem, op->idx, G, Bb, u + c * cs,
                        w + c * cs, op->ncomp, c, masked, part, done, owned(op));
   return BP_OK;
 }
@@ -77,6 +76,16 @@ int mass_colloc(const bp_op_s *op, const T *Bt, const T *u, T *w, int masked, do
   return BP_OK;
 }
 
+// Several Gauss-Legendre components in one launch of k_op_gl_nc (G and the
+// map read once per element for all of them) where G beside a component's
+// working set fits 256 registers: the mass operator, p1 <= 7, and the
+// stiffness operator when the point values fit the pencil's LDS rows (p1
+// even). Otherwise (p1 = 9, the Helmholtz form at p1 = 8) the multi-component
+// kernel spills and each component gets its own launch.
+constexpr bool gl_multi(int p1, int q, int mode) {
+  return mode == kGLMass || p1 <= 7 || (mode == kGLStiff && gl_row_stride(p1) >= q);
+}
+
 // WL: u global, w element-local [ncomp][nelem][p1^3] (see k_op_gl)
 template <int P1, int Q, typename T, int MODE, bool LOCAL, bool WL = false>
 int gauss(const bp_op_s *op, const T *Gm, const T *Bb, const T *basis, const T *u, T *w,
@@ -87,6 +96,14 @@ int gauss(const bp_op_s *op, const T *Gm, const T *Bb, const T *basis, const T *
   if (grid != apply_rows(op, MODE == kGLMass ? BP_MASS : BP_STIFF))
     return set_error(BP_ERR_ARG, "plane layout");
   const int64_t cs = vec_stride<LOCAL>(op), ws = WL ? vec_stride<true>(op) : cs;
+  if constexpr (gl_multi(P1, Q, MODE)) {
+    if (op->ncomp > 1) {
+      hipLaunchKernelGGL((k_op_gl_nc<P1, Q, T, MODE, LOCAL, WL>), dim3(grid), dim3(PL::THREADS),
+                         0, s, op->nelem, op->idx, Gm, Bb, basis, u, w, cs, ws, op->ncomp,
+                         masked, part, done, owned(op));
+      return BP_OK;
+    }
+  }
   for (int c = 0; c < op->ncomp; ++c)
     hipLaunchKernelGGL((k_op_gl<P1, Q, T, MODE, LOCAL, WL>), dim3(grid), dim3(PL::THREADS), 0,
                        s, op->nelem, op->idx, Gm, Bb, basis, u + c * cs, w + c * ws, op->ncomp,
@@ -154,7 +171,7 @@ void grad_colloc(const bp_op_s *op, const double *lam, const double *u, double *
                  hipStream_t s) {
   using PL = Plane<P1, P1>;
   hipLaunchKernelGGL((k_grad_kappa_colloc<P1>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
-                     op->nelem, op->idx, op->G, op->basis_d, lam, u, g, op->nglobal, op->ncomp);
+                     op->nelem, op->idx, op->G, lam, u, g, op->nglobal, op->ncomp);
 }
 
 }  // namespace

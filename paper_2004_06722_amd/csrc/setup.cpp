@@ -1,4 +1,5 @@
-// Host-side setup of the bake-off operators: 1D rules and Lagrange matrices
+// Host-side setup of the bake-off operators: the 1D basis of an operator
+// (rules and Lagrange matrices from rules1d.hpp) and the internal node order
 // (the geometric factors of section 3 are computed on the device at set-up).
 #include <algorithm>
 #include <cmath>
@@ -6,158 +7,6 @@
 #include "bp_internal.h"
 
 namespace bp {
-
-namespace {
-
-// P_n(x) and P_{n-1}(x) by the three-term recurrence (k+1)P_{k+1} =
-// (2k+1) x P_k - k P_{k-1}.
-void legendre_pair(int n, double x, double *pn, double *pnm1) {
-  double a = 1.0, b = x;  // P_0, P_1
-  if (n == 0) {
-    *pn = 1.0;
-    *pnm1 = 0.0;
-    return;
-  }
-  for (int k = 1; k < n; ++k) {
-    double c = ((2 * k + 1) * x * b - k * a) / (k + 1);
-    a = b;
-    b = c;
-  }
-  *pn = b;
-  *pnm1 = a;
-}
-
-double legendre(int n, double x) {
-  double pn, pm;
-  legendre_pair(n, x, &pn, &pm);
-  return pn;
-}
-
-}  // namespace
-
-// GLL points: the zeros of (1 - x^2) P_p'(x), which are the zeros of
-// f = P_{p+1} - P_{p-1} (f' = (2p+1) P_p). Weights 2 / (p (p+1) P_p(x)^2).
-void gll_rule(int n, double *x, double *w) {
-  const int p = n - 1;
-  const double pi = 3.14159265358979323846;
-  for (int j = 0; j < n; ++j) {
-    double t = -std::cos(pi * j / p);
-    if (j > 0 && j < p) {
-      for (int it = 0; it < 100; ++it) {
-        double pp1 = legendre(p + 1, t), pm1 = legendre(p - 1, t);
-        double dt = (pp1 - pm1) / ((2 * p + 1) * legendre(p, t));
-        t -= dt;
-        if (std::fabs(dt) < 1e-16) break;
-      }
-    }
-    x[j] = t;
-  }
-  x[0] = -1.0;
-  x[p] = 1.0;
-  // exact symmetry
-  for (int j = 0; j < n / 2; ++j) {
-    double s = 0.5 * (x[n - 1 - j] - x[j]);
-    x[j] = -s;
-    x[n - 1 - j] = s;
-  }
-  if (n % 2) x[n / 2] = 0.0;
-  if (w)
-    for (int j = 0; j < n; ++j) {
-      double lp = legendre(p, x[j]);
-      w[j] = 2.0 / (p * (p + 1) * lp * lp);
-    }
-}
-
-// GL points: zeros of P_n; P_n' = n (x P_n - P_{n-1}) / (x^2 - 1).
-// Weights 2 / ((1 - x^2) P_n'(x)^2).
-void gl_rule(int n, double *x, double *w) {
-  const double pi = 3.14159265358979323846;
-  for (int j = 0; j < n; ++j) {
-    double t = -std::cos(pi * (j + 0.75) / (n + 0.5));
-    double dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
-      double pn, pm;
-      legendre_pair(n, t, &pn, &pm);
-      dp = n * (t * pn - pm) / (t * t - 1.0);
-      double dt = pn / dp;
-      t -= dt;
-      if (std::fabs(dt) < 1e-16) break;
-    }
-    double pn, pm;
-    legendre_pair(n, t, &pn, &pm);
-    dp = n * (t * pn - pm) / (t * t - 1.0);
-    x[j] = t;
-    if (w) w[j] = 2.0 / ((1.0 - t * t) * dp * dp);
-  }
-  for (int j = 0; j < n / 2; ++j) {
-    double s = 0.5 * (x[n - 1 - j] - x[j]);
-    x[j] = -s;
-    x[n - 1 - j] = s;
-    if (w) {
-      double ws = 0.5 * (w[j] + w[n - 1 - j]);
-      w[j] = w[n - 1 - j] = ws;
-    }
-  }
-  if (n % 2) x[n / 2] = 0.0;
-}
-
-// Barycentric weights lambda_j = 1 / prod_{m != j} (x_j - x_m).
-static std::vector<double> bary_weights(int n, const double *nodes) {
-  std::vector<double> lam(n, 1.0);
-  for (int j = 0; j < n; ++j)
-    for (int m = 0; m < n; ++m)
-      if (m != j) lam[j] /= (nodes[j] - nodes[m]);
-  return lam;
-}
-
-static int node_hit(int n, const double *nodes, double x) {
-  for (int m = 0; m < n; ++m)
-    if (x == nodes[m]) return m;
-  return -1;
-}
-
-void lagrange_interp(int n, const double *nodes, int m, const double *pts, double *out) {
-  auto lam = bary_weights(n, nodes);
-  for (int a = 0; a < m; ++a) {
-    double *row = out + (size_t)a * n;
-    int hit = node_hit(n, nodes, pts[a]);
-    if (hit >= 0) {
-      for (int j = 0; j < n; ++j) row[j] = (j == hit) ? 1.0 : 0.0;
-      continue;
-    }
-    double den = 0.0;
-    for (int j = 0; j < n; ++j) den += lam[j] / (pts[a] - nodes[j]);
-    for (int j = 0; j < n; ++j) row[j] = lam[j] / (pts[a] - nodes[j]) / den;
-  }
-}
-
-// At a node x_a: D_aj = (lam_j / lam_a) / (x_a - x_j), D_aa = -sum_{j != a} D_aj.
-// Elsewhere: h_j'(x) = h_j(x) * sum_{m != j} 1 / (x - x_m).
-void lagrange_deriv(int n, const double *nodes, int m, const double *pts, double *out) {
-  auto lam = bary_weights(n, nodes);
-  std::vector<double> h(n);
-  for (int a = 0; a < m; ++a) {
-    double *row = out + (size_t)a * n;
-    int hit = node_hit(n, nodes, pts[a]);
-    if (hit >= 0) {
-      double diag = 0.0;
-      for (int j = 0; j < n; ++j) {
-        if (j == hit) continue;
-        row[j] = (lam[j] / lam[hit]) / (nodes[hit] - nodes[j]);
-        diag -= row[j];
-      }
-      row[hit] = diag;
-      continue;
-    }
-    lagrange_interp(n, nodes, 1, &pts[a], h.data());
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < n; ++k)
-        if (k != j) s += 1.0 / (pts[a] - nodes[k]);
-      row[j] = h[j] * s;
-    }
-  }
-}
 
 Basis make_basis(int p, int q, int quad) {
   Basis b;

@@ -88,7 +88,7 @@ def test_zero_beta_is_stiffness_and_beta_can_be_reset():
         c.close()
 
 
-@pytest.mark.parametrize("bp,p,ncomp", [(5, 7, 1), (5, 3, 3), (3, 4, 1), (3, 7, 2)])
+@pytest.mark.parametrize("bp,p,ncomp", [(5, 7, 1), (5, 3, 3), (3, 4, 1), (3, 7, 2), (3, 5, 3)])
 def test_helmholtz_pcg_iterates_match_oracle(bp, p, ncomp):
     c = Case(bp, p, *((3, 3, 3) if p <= 4 else (3, 2, 2)), seed=72, ncomp=ncomp)
     try:

@@ -53,7 +53,7 @@ def test_apply_local_matches_oracle(bp, p):
         c.close()
 
 
-@pytest.mark.parametrize("bp,p,ncomp", [(6, 7, 3), (4, 3, 3), (2, 5, 2)])
+@pytest.mark.parametrize("bp,p,ncomp", [(6, 7, 3), (4, 3, 3), (4, 7, 3), (4, 6, 2), (2, 5, 2)])
 def test_apply_local_vector_components(bp, p, ncomp):
     c = Case(bp, p, 3, 2, 2, seed=7, ncomp=ncomp)
     try:

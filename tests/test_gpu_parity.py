@@ -70,6 +70,34 @@ def test_vector_components_match_oracle(bp, p, ncomp):
         c.close()
 
 
+@pytest.mark.parametrize("p", range(1, 9))
+def test_gauss_legendre_vector_components_every_order(p):
+    # ncomp = 3 with Gauss-Legendre quadrature (BP2 and BP4 on one mesh): the
+    # multi-component launch at every order, in both of its stage-3 forms
+    # (point values staged in LDS for even p1, registers for odd p1) and the
+    # per-component launches it falls back to at p = 8; the energies p.Ap of
+    # all components come from the same launch
+    c = Case(4, p, *grid_for(p), seed=30 + p, ncomp=3)
+    try:
+        u = c.vec(31)
+        for which in (MASS, STIFF):
+            for masked in (False, True):
+                w = host(c.op.apply(which, dev(u), masked=masked))
+                ref = c.disc.apply(which, u, masked=masked)
+                for k in range(3):
+                    assert rel(w[:, k], ref[:, k]) <= TOL, (which, masked, k)
+        mask = 1 - c.mesh.boundary
+        b = c.vec(32) * mask[:, None]
+        rec = []
+        pcg(lambda v: c.disc.apply(STIFF, v, masked=True), b,
+            c.disc.jacobi_inverse(STIFF, masked=True), maxit=6, fixed_iters=True, record=rec)
+        for k in (1, 6):
+            x, _ = c.op.pcg_solve(dev(b), which=STIFF, maxit=k, fixed_iters=True)
+            assert rel(host(x), rec[k - 1]) <= TOL, k
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("bp,p", [(1, 2), (1, 7), (3, 1), (3, 5), (3, 8), (5, 1), (5, 4), (5, 7), (5, 8)])
 def test_diagonal_matches_oracle(bp, p):
     c = Case(bp, p, *grid_for(p), seed=4)
