@@ -66,6 +66,23 @@ struct DevScalars {
   int pad_[2];
 };
 
+// Operands of the two-launch iteration of small meshes (k_stiff_colloc_pz
+// and the vector kernel k_cg_update_rxp_fused; one component): the operator
+// applies A to p_k = z_k + beta_{k-1} p_{k-1}, formed at the gathered nodes
+// from the stored z_k and p_{k-1}, with beta_{k-1} = (r_k.z_k) /
+// (r_{k-1}.z_{k-1}) from the vector kernel's partial rows; the vector kernel
+// then stores p_k (same expression, same beta). r.z by iteration parity:
+// iteration k's operator launch writes rzs[k & 1].
+struct PZIter {
+  const double *z;   // z_k = dinv r_k, [n]
+  const double *pr;  // partial rows [nbv][2]: r_k.z_k, r_k.r_k
+  int64_t nbv;
+  DevScalars *sc;
+  int parity;  // k & 1
+  int check;   // a stopping test is honoured (not fixed iterations)
+  int first;   // k = 0: p_0 = z_0 is stored already; nothing to reduce
+};
+
 }  // namespace bp
 
 // The operator object.
@@ -99,7 +116,7 @@ struct bp_op_s {
   bool time_apply = false;
   int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
   int cg_variant = 0;  // BP_CG_STANDARD or BP_CG_SINGLE_REDUCTION (bp_pcg_solve)
-  bool cg_fuse = true; // BP_OPT_CG_FUSE: the fused iteration on small meshes
+  int cg_fuse = 2;  // BP_OPT_CG_FUSE: the fused iteration on small meshes (0 off, 1, 2)
   double *sv = nullptr;  // s = A p of the single-reduction PCG (allocated when selected)
   // Gauss-Legendre operators: the gather map transposed (CSR over global
   // nodes: the element-local slots e p1^3 + l of node g are

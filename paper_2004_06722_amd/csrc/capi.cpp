@@ -305,12 +305,27 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
   // updates, three launches per iteration; the operator's partials stay at
   // the start of `part`, the residual update's follow them
   const bool fused =
-      op->cg_fuse && sizeof(T) == 8 && !mass_wl && !resume && cg_fused_fits(n, nb_apply);
+      op->cg_fuse > 0 && sizeof(T) == 8 && !mass_wl && !resume && cg_fused_fits(n, nb_apply);
+  // two launches per iteration where the operator forms p itself (PZIter)
+  const bool fused2 = fused && op->cg_fuse == 2 && apply_pz_supported(op, which);
   double *const part_r = part + nb_apply * nc;
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
     for (int c = 0; c < chunk; ++c) {
       const bool tm = op->time_apply && timed < kMaxTimedApplies;
+      if constexpr (sizeof(T) == 8) {
+        if (fused2) {
+          const int k = it + c;
+          const PZIter pz{r, part_r, vec_blocks(n), sc, k & 1, check ? 1 : 0, k == 0 ? 1 : 0};
+          if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
+          rc = launch_apply_pz(op, p, w, masked, part, done, pz, s);
+          if (rc) return rc;
+          if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
+          cg_update_rxp_fused(nc, n, x, p, r, w, dinv, part, nb_apply, part_r, sc, k & 1, s,
+                              check, k == 0, stored_rows(op, which));
+          continue;
+        }
+      }
       if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
       rc = mass_wl ? launch_mass_wl(op, f32, p, masked, part, done, s)
                    : launch_apply(op, which, f32, p, w, masked, part, done, s);
@@ -343,6 +358,9 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
     }
   }
   BP_HIP(hipEventRecord(op->ev1, s));
+  if constexpr (sizeof(T) == 8) {
+    if (fused2 && it > 0) cg_fin_rxp_fused(nc, n, part_r, sc, s);  // r.z, r.r of the last x
+  }
   rc = download_scalars(op, sc, s);
   if (rc) return rc;
   float ms = 0.0f;
@@ -1093,8 +1111,8 @@ int bp_set_option(bp_op op, int option, int value) {
     return BP_OK;
   }
   if (option == BP_OPT_CG_FUSE) {
-    if (value != 0 && value != 1) return set_error(BP_ERR_ARG, "bp_set_option: CG fuse 0 or 1");
-    op->cg_fuse = value != 0;
+    if (value < 0 || value > 2) return set_error(BP_ERR_ARG, "bp_set_option: CG fuse 0, 1 or 2");
+    op->cg_fuse = value;
     return BP_OK;
   }
   if (option == BP_OPT_MIXED_MODE) {

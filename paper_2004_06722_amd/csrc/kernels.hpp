@@ -11,6 +11,7 @@
 // sum_e u_L^T w_L (Appendix A1: rho = w^T u before assembly) is reduced per
 // work-group into a partial sum.
 #pragma once
+#include "bp_internal.h"
 #include "rules1d.hpp"
 
 #include <hip/hip_runtime.h>
@@ -76,6 +77,57 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *out, in
     }
 }
 
+// Column sums of a partial table part[nb][2] (r.z and r.r of one component)
+// in one fixed order, split in two steps so that the loads of the first U
+// rows per thread are in flight together with the operator's map and G:
+// thread t adds rows t, t + THREADS, ... in turn; a fixed shuffle tree per
+// wave; the waves' sums in order. Every work-group obtains bit-identical sums.
+template <int THREADS>
+struct RowPairSums {
+  static constexpr int U = 8;
+  double v[U][2];
+  __device__ __forceinline__ void issue(const double *__restrict__ part, int64_t nb) {
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t r = threadIdx.x + (int64_t)q * THREADS;
+      v[q][0] = r < nb ? part[2 * r] : 0.0;
+      v[q][1] = r < nb ? part[2 * r + 1] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void finish(const double *__restrict__ part, int64_t nb,
+                                         double *res) {
+    constexpr int NW = THREADS / 64;
+    __shared__ double red[NW][2];
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      a0 += v[q][0];
+      a1 += v[q][1];
+    }
+    for (int64_t r = threadIdx.x + (int64_t)U * THREADS; r < nb; r += THREADS) {
+      a0 += part[2 * r];
+      a1 += part[2 * r + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a0 += __shfl_down(a0, o, 64);
+      a1 += __shfl_down(a1, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6][0] = a0;
+      red[threadIdx.x >> 6][1] = a1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      double x = 0.0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) x += red[k][threadIdx.x];
+      res[threadIdx.x] = x;
+    }
+    __syncthreads();
+  }
+};
+
 // Element-interior local node (0 < i, j, k < P1 - 1): with the internal node
 // order (own != 0) no other element touches it, so the scatter stores its
 // value instead of adding it atomically (its internal id lies in a block of
@@ -97,11 +149,12 @@ __device__ __forceinline__ int decode_index(int v, bool live, int masked) {
 // every component of u and w ([ncomp][cs]) runs through one work-group, G and
 // the map loaded once; otherwise the one component that u and w point at
 // (energy column c0).
-template <int P1, typename T, bool LOCAL, bool HELM, bool MULTI>
+template <int P1, typename T, bool LOCAL, bool HELM, bool MULTI, bool PZ = false>
 __device__ __forceinline__ void stiff_colloc_body(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
     const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int64_t cs, int ncomp,
-    int c0, int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
+    int c0, int masked, double *__restrict__ part, const int *__restrict__ done, int own,
+    PZIter pz = {}) {
   constexpr int NC = 1;  // LDS tiles of one component at a time
   static constexpr GLLDeriv<P1, T> kD{};  // D^, compile-time constants
   const T *const Dg = kD.D;
@@ -123,6 +176,21 @@ __device__ __forceinline__ void stiff_colloc_body(
   __shared__ T su[PL::EPB][NC][P1][P1][PAD];
   __shared__ T sr[PL::EPB][NC][P1][P1][PAD];
   __shared__ T ss[PL::EPB][NC][P1][P1][PAD];
+  // two-launch iteration (PZIter, one component): the scalars and the
+  // partial rows of r_k.z_k and r_k.r_k are requested first
+  RowPairSums<PL::THREADS> pzs;
+  double pz_rzo = 0.0, pz_bb = 1.0, pz_tol2 = 0.0;
+  int pz_fixed = 1;
+  if constexpr (PZ) {
+    if (!pz.first) {
+      const DevScalars *sc = pz.sc;
+      pz_rzo = sc->rzs[pz.parity ^ 1][0];
+      pz_bb = sc->bb[0];
+      pz_tol2 = sc->tol2;
+      pz_fixed = sc->fixed;
+      pzs.issue(pz.pr, pz.nbv);
+    }
+  }
   // one round trip: the column of the gather map and of G
   const int32_t *ie = idx + ec * N3 + ij;
   const T *Ge = G + ec * 6 * N3 + ij;
@@ -152,18 +220,54 @@ __device__ __forceinline__ void stiff_colloc_body(
     if (!LOCAL) gk[k] = v >= 0 ? v : -1 - v;
   }
 
+  // two-launch iteration (PZIter): z_k and p_{k-1} gathered before the
+  // partial sums are finished (their loads in flight meanwhile); r_k.z_k and
+  // r_k.r_k, the same in every work-group; the stopping test on r_k ends the
+  // launch in all of them at once; p_k = z_k + beta p_{k-1} at the nodes
+  T pzp[PZ ? P1 : 1], pzz[PZ ? P1 : 1];
+  __shared__ double pzr[2];
+  double pz_beta = 0.0;
+  if constexpr (PZ) {
+    static_assert(!MULTI, "the two-launch iteration runs one component");
+#pragma unroll
+    for (int k = 0; k < P1; ++k) {
+      pzp[k] = u[gk[k]];
+      pzz[k] = pz.first ? T(0) : pz.z[gk[k]];
+    }
+    if (!pz.first) {
+      pzs.finish(pz.pr, pz.nbv, pzr);
+      const double bb = pz_bb > 0.0 ? pz_bb : 1.0;
+      const bool conv = !pz_fixed && pzr[1] <= pz_tol2 * bb;
+      const bool bad = !isfinite(pzr[0]) || !isfinite(pzr[1]);
+      const bool stop = pz.check && (conv || bad);
+      pz_beta = pz_rzo != 0.0 ? pzr[0] / pz_rzo : 0.0;
+      if (blockIdx.x == 0 && t == 0) {
+        DevScalars *sc = pz.sc;
+        sc->rzs[pz.parity][0] = sc->rz[0] = pzr[0];
+        sc->rzp[0] = pz_rzo;
+        sc->rr[0] = pzr[1];
+        sc->beta[0] = pz_beta;
+        if (bad) sc->nonfinite = 1;
+        if (stop) sc->done = sc->halted = 1;  // x_k is the answer
+      }
+      if (stop) return;
+#pragma unroll
+      for (int k = 0; k < P1; ++k) pzp[k] = __builtin_fma(pz_beta, pzp[k], pzz[k]);
+    }
+  }
+
   const int nrun = MULTI ? ncomp : 1;
 #pragma unroll 1
   for (int cc = 0; cc < nrun; ++cc) {
     const T *uc = u + (MULTI ? cc * cs : 0);
     T *wc = w + (MULTI ? cc * cs : 0);
-    // gather u
+    // gather u (PZ: p_k, formed above as the vector kernel forms it)
     T ru[NC][P1];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int k = 0; k < P1; ++k) {
-        const T v = uc[gk[k]];
+        const T v = PZ ? pzp[PZ ? k : 0] : uc[gk[k]];
         ru[c][k] = (mb >> k & 1u) ? v : T(0);
       }
     if (cc == 0) {
@@ -286,6 +390,18 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
     int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
   stiff_colloc_body<P1, T, LOCAL, HELM, false>(nelem, idx, G, Bb, u, w, 0, ncomp, c0, masked,
                                                part, done, own);
+}
+
+// The operator of the two-launch iteration (PZIter): p_k formed at the
+// gathered nodes from z_k and p_{k-1}, FP64, assembled output.
+// One component (ncomp = 1): u = p_{k-1} (p_0 at k = 0), pz.z = z_k.
+template <int P1>
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc_pz(
+    int64_t nelem, const int32_t *__restrict__ idx, const double *__restrict__ G,
+    const double *__restrict__ u, double *__restrict__ w, int ncomp, int c0, int masked,
+    double *__restrict__ part, const int *__restrict__ done, int own, PZIter pz) {
+  stiff_colloc_body<P1, double, false, false, false, true>(
+      nelem, idx, G, nullptr, u, w, 0, ncomp, c0, masked, part, done, own, pz);
 }
 
 template <int P1, typename T, bool LOCAL = false, bool HELM = false>

@@ -95,6 +95,22 @@ void cg_update_xp_fused(int nc, int64_t n, double *x, double *p, const double *z
                         const double *pr, DevScalars *sc, int parity, hipStream_t s,
                         bool check);
 
+// The two-launch iteration of small meshes (FP64, collocated stiffness, one
+// component, p1 <= 9; PZIter): the operator launch forms p_k = z_k + beta p_{k-1} while
+// gathering and takes the stopping test on r_k; cg_update_rxp_fused then
+// stores p_k, updates x and z = dinv r and writes the partials of the next
+// r.z and r.r into pr. cg_fin_rxp_fused, once after the last iteration,
+// reduces pr into the scalars the host reads (r.z, r.r, and the stopping
+// test of the last iterate).
+bool apply_pz_supported(const bp_op_s *op, int which);
+int launch_apply_pz(const bp_op_s *op, const double *p, double *w, bool masked, double *part,
+                    const int *done, const PZIter &pz, hipStream_t s);
+void cg_update_rxp_fused(int nc, int64_t n, double *x, double *p, double *z, double *w,
+                         const double *dinv, const double *pa, int64_t nba, double *pr,
+                         DevScalars *sc, int parity, hipStream_t s, bool check, bool first,
+                         int64_t n_own);
+void cg_fin_rxp_fused(int nc, int64_t n, const double *pr, DevScalars *sc, hipStream_t s);
+
 // transposed gather Q^T w_L: w[c][g] += sum of wl[c][pos[k]] for k in
 // [off[g], off[g+1]) in ascending order (wl is [nc][nl]); skipped while
 // *done (done may be NULL)

@@ -166,6 +166,18 @@ int dispatch(const bp_op_s *op, int which, const T *G, const T *Bt, const T *Bb,
   return set_error(BP_ERR_ARG, "no compiled kernel for this (p, q, quadrature)");
 }
 
+// The operator of the two-launch iteration (PZIter): collocated stiffness,
+// one component.
+template <int P1>
+int stiff_colloc_pz(const bp_op_s *op, const double *G, const double *p, double *w, int masked,
+                    double *part, const int *done, const PZIter &pz, hipStream_t s) {
+  using PL = Plane<P1, P1>;
+  hipLaunchKernelGGL((k_stiff_colloc_pz<P1>), dim3(apply_blocks(op)), dim3(PL::THREADS), 0, s,
+                     op->nelem, op->idx, G, p, w, op->ncomp, 0, masked, part, done, owned(op),
+                     pz);
+  return BP_OK;
+}
+
 template <int P1>
 void grad_colloc(const bp_op_s *op, const double *lam, const double *u, double *g,
                  hipStream_t s) {
@@ -236,6 +248,31 @@ int launch_apply(const bp_op_s *op, int which, bool f32, const void *u, void *w,
     return BP_OK;
   }
   return launch_apply_impl<false>(op, which, f32, u, w, masked, part, done, s);
+}
+
+bool apply_pz_supported(const bp_op_s *op, int which) {
+  return op->colloc && which == BP_STIFF && op->ncomp == 1 && op->p1 >= 2 && op->p1 <= 9;
+}
+
+int launch_apply_pz(const bp_op_s *op, const double *p, double *w, bool masked, double *part,
+                    const int *done, const PZIter &pz, hipStream_t s) {
+  if (!apply_pz_supported(op, BP_STIFF))
+    return set_error(BP_ERR_ARG,
+                     "two-launch iteration: collocated stiffness, one component, p <= 8");
+  const double *G = op->kappa_set ? op->Gk : op->G;
+  const int m = masked ? 1 : 0;
+  int rc = BP_OK;
+  switch (op->p1) {
+#define BP_CASE(P) \
+  case P:          \
+    rc = stiff_colloc_pz<P>(op, G, p, w, m, part, done, pz, s); \
+    break;
+    BP_CASE(2) BP_CASE(3) BP_CASE(4) BP_CASE(5) BP_CASE(6) BP_CASE(7) BP_CASE(8) BP_CASE(9)
+#undef BP_CASE
+  }
+  if (rc != BP_OK) return rc;
+  BP_HIP(hipGetLastError());
+  return BP_OK;
 }
 
 int launch_apply_local(const bp_op_s *op, int which, bool f32, const void *uL, void *wL,

@@ -644,6 +644,98 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xp_fused(
   }
 }
 
+// The vector kernel of the two-launch iteration (PZIter): the operator has
+// applied A to p_k = z_k + beta p_{k-1} and stored r_k.z_k into rzs[parity]
+// and beta into sc->beta (iteration 0: p_0 = z_0, stored by the
+// initialisation). alpha from the operator's partials pa[nba][NC]; per node
+// p_k (stored), x += alpha p_k, z_{k+1} = z_k - alpha dinv w_k, w zeroed at
+// the nodes the operator adds into (v >= n_own); partials of r_{k+1}.z_{k+1}
+// and r_{k+1}.r_{k+1} into pr for the next operator launch. A breakdown or a
+// non-finite p.Ap ends the solve as in k_cg_update_r_fused.
+template <int NC>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_rxp_fused(
+    int64_t n, double *__restrict__ x, double *__restrict__ p, double *__restrict__ z,
+    double *__restrict__ w, const double *__restrict__ dinv, const double *__restrict__ pa,
+    int64_t nba, double *__restrict__ pr, DevScalars *sc, int parity, int check, int first,
+    int64_t n_own) {
+  if (check && sc->done) return;  // x_k met the stopping test in the operator launch
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const bool in = v < n;
+  double di = 0.0, zo[NC], wo[NC], po[NC], xo[NC];
+  if (in) {  // requested before the reduction
+    di = dinv[v];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      zo[c] = z[c * n + v];
+      wo[c] = w[c * n + v];
+      po[c] = p[c * n + v];
+      xo[c] = x[c * n + v];
+    }
+  }
+  __shared__ double pap[NC];
+  block_reduce_rows<NC>(pa, nba, pap);
+  double al[NC], be[NC];
+  int bad = 0, brk = 0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double rz = sc->rzs[parity][c];
+    al[c] = pap[c] != 0.0 ? rz / pap[c] : 0.0;
+    be[c] = first ? 0.0 : sc->beta[c];
+    brk |= indefinite(rz, pap[c]);
+    bad |= !isfinite(pap[c]);
+  }
+  const bool stop = check && (brk || bad);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int c = 0; c < NC; ++c) {
+      sc->pap[c] = pap[c];
+      sc->alpha[c] = al[c];
+    }
+    if (brk) sc->breakdown = 1;
+    if (bad) sc->nonfinite = 1;
+    if (stop)
+      sc->done = sc->halted = 1;
+    else
+      sc->iters += 1;
+  }
+  if (stop) return;
+  double acc[2 * NC];
+#pragma unroll
+  for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
+  if (in) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double pk = first ? po[c] : __builtin_fma(be[c], po[c], zo[c]);
+      if (!first) p[c * n + v] = pk;
+      x[c * n + v] = xo[c] + al[c] * pk;
+      const double zv = zo[c] - (al[c] * di) * wo[c];
+      z[c * n + v] = zv;
+      if (v >= n_own) w[c * n + v] = 0.0;
+      const double rv = di != 0.0 ? zv / di : 0.0;
+      acc[c] = rv * zv;
+      acc[NC + c] = rv * rv;
+    }
+  }
+  block_partials<2 * NC>(acc, pr);
+}
+
+// After the last iteration of the two-launch form: r.z and r.r of the last
+// iterate from the partials pr, and its stopping test.
+template <int NC>
+__global__ __launch_bounds__(kFinThreads) void k_fin_rxp_fused(const double *__restrict__ pr,
+                                                               int64_t nb, DevScalars *sc) {
+  constexpr int nc = NC;
+  __shared__ double res[2 * NC];
+  reduce_columns<2 * NC>(pr, nb, res);
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < nc; ++c) {
+      sc->rz[c] = res[c];
+      sc->rr[c] = res[nc + c];
+      if (!isfinite(res[c]) || !isfinite(res[nc + c])) sc->nonfinite = 1;
+    }
+    if (!sc->done && !sc->fixed && converged(sc, nc)) sc->done = 1;
+  }
+}
+
 // w[c][v] += Q^T w_L at node v (fixed order as above), one node per thread
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_gather_local(
@@ -1240,6 +1332,44 @@ static void launch_fused(bool residual, int nc, int64_t n, double *x, double *p,
     default: BP_FUSED(kMaxComp); break;
   }
 #undef BP_FUSED
+}
+
+void cg_update_rxp_fused(int nc, int64_t n, double *x, double *p, double *z, double *w,
+                         const double *dinv, const double *pa, int64_t nba, double *pr,
+                         DevScalars *sc, int parity, hipStream_t s, bool check, bool first,
+                         int64_t n_own) {
+#define BP_RXP(NC)                                                                          \
+  hipLaunchKernelGGL((k_cg_update_rxp_fused<NC>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, \
+                     s, n, x, p, z, w, dinv, pa, nba, pr, sc, parity, check ? 1 : 0,         \
+                     first ? 1 : 0, n_own)
+  switch (nc) {
+    case 1: BP_RXP(1); break;
+    case 2: BP_RXP(2); break;
+    case 3: BP_RXP(3); break;
+    case 4: BP_RXP(4); break;
+    case 5: BP_RXP(5); break;
+    case 6: BP_RXP(6); break;
+    case 7: BP_RXP(7); break;
+    default: BP_RXP(kMaxComp); break;
+  }
+#undef BP_RXP
+}
+
+void cg_fin_rxp_fused(int nc, int64_t n, const double *pr, DevScalars *sc, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+#define BP_FIN(NC) \
+  hipLaunchKernelGGL((k_fin_rxp_fused<NC>), dim3(1), dim3(kFinThreads), 0, s, pr, nb, sc)
+  switch (nc) {
+    case 1: BP_FIN(1); break;
+    case 2: BP_FIN(2); break;
+    case 3: BP_FIN(3); break;
+    case 4: BP_FIN(4); break;
+    case 5: BP_FIN(5); break;
+    case 6: BP_FIN(6); break;
+    case 7: BP_FIN(7); break;
+    default: BP_FIN(kMaxComp); break;
+  }
+#undef BP_FIN
 }
 
 bool cg_fused_fits(int64_t n, int64_t nb_apply) {

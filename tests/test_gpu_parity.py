@@ -170,17 +170,21 @@ def manufactured_rhs(c):
     return c.disc.apply(MASS, f, masked=False) * c.disc.mask
 
 
-@pytest.mark.parametrize("fuse", [True, False])
-@pytest.mark.parametrize("bp,p,ncomp", [(5, 2, 1), (5, 4, 1), (5, 5, 1), (5, 6, 2), (5, 7, 1),
-                                         (5, 5, 8), (3, 4, 1), (3, 6, 1), (1, 5, 1)])
+@pytest.mark.parametrize("fuse", [2, 1, 0])
+@pytest.mark.parametrize("bp,p,ncomp", [(5, 1, 1), (5, 2, 1), (5, 4, 1), (5, 5, 1), (5, 6, 2),
+                                         (5, 7, 1), (5, 7, 3), (5, 8, 2), (5, 5, 8), (3, 4, 1),
+                                         (3, 6, 1), (1, 5, 1)])
 def test_pcg_iterates_match_oracle_orders(bp, p, ncomp, fuse):
     # every order's thread plane (including planes that leave idle lanes in a
     # wave) and several components: the fused energy p.Ap drives alpha; with
-    # fuse the vector updates compute alpha and beta themselves (small meshes)
+    # fuse 1 the vector updates compute alpha and beta themselves (small
+    # meshes), with fuse 2 the collocated stiffness operator of one component
+    # also forms the direction p = z + beta p while it gathers (two launches
+    # per iteration; several components keep the three-launch form)
     from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
     c = Case(bp, p, *grid_for(p), seed=21, ncomp=ncomp)
     try:
-        c.op.set_option(BP_OPT_CG_FUSE, 1 if fuse else 0)
+        c.op.set_option(BP_OPT_CG_FUSE, fuse)
         which = MASS if bp == 1 else STIFF
         mask = (1 - c.mesh.boundary) if bp >= 3 else np.ones(c.disc.nglobal)
         b = c.vec(3) * (mask[:, None] if ncomp > 1 else mask)
@@ -265,13 +269,13 @@ def test_pcg_iterates_match_oracle_config1():
         c.close()
 
 
-@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("fuse", [2, 1, 0])
 def test_pcg_converged_solution_config1(fuse):
     import scipy.sparse.linalg as spla
     from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
     c = Case(5, 3, 4, 4, 4, seed=0)
     try:
-        c.op.set_option(BP_OPT_CG_FUSE, 1 if fuse else 0)
+        c.op.set_option(BP_OPT_CG_FUSE, fuse)
         b = manufactured_rhs(c)
         x, st = c.op.pcg_solve(dev(b), rtol=1e-14, maxit=5000)
         assert st["converged"] and st["rel_res"][0] <= 1e-14
