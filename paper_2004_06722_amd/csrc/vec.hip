@@ -719,11 +719,14 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_rxp_fused(
 }
 
 // After the last iteration of the two-launch form: r.z and r.r of the last
-// iterate from the partials pr, and its stopping test.
+// iterate from the partials pr, and its stopping test. Nothing to do once
+// the solve halted (a stopping test met in an operator launch, which stored
+// these scalars itself, or a breakdown, after which pr holds no new rows).
 template <int NC>
 __global__ __launch_bounds__(kFinThreads) void k_fin_rxp_fused(const double *__restrict__ pr,
                                                                int64_t nb, DevScalars *sc) {
   constexpr int nc = NC;
+  if (sc->halted) return;
   __shared__ double res[2 * NC];
   reduce_columns<2 * NC>(pr, nb, res);
   if (threadIdx.x == 0) {

@@ -270,6 +270,57 @@ def test_pcg_iterates_match_oracle_config1():
 
 
 @pytest.mark.parametrize("fuse", [2, 1, 0])
+def test_indefinite_coefficient_reports_breakdown(fuse):
+    # kappa = -2 at the quadrature points within 0.15 of the centre and 1
+    # elsewhere makes the BP5 stiffness indefinite while its diagonal stays
+    # positive on the free nodes, and for the smooth rhs M f the first step
+    # has r.z > 0 and p.Ap < 0 (checked on the oracle below). Every CG form,
+    # the two-launch one included, stops there with BP_ERR_BREAKDOWN and
+    # x = 0; the fixed-count mode runs every iteration and reports it at the
+    # end.
+    import ctypes
+
+    from oracle.geometry import quad_points
+    from paper_2004_06722_amd import _lib
+    c = Case(5, 3, 3, 3, 3, seed=66)
+    try:
+        xyz = quad_points(c.disc.rule, c.mesh.node_xyz)
+        kap = np.where(((xyz - 0.5) ** 2).sum(-1) < 0.15 ** 2, -2.0, 1.0)
+        kd = Discretization(c.disc.rule, c.mesh.elem_dofs, c.mesh.node_xyz, c.disc.nglobal,
+                            c.dir, kappa=kap)
+        f = synth.manufactured_f(c.mesh.global_coords())
+        bh = c.disc.apply(MASS, f, masked=False) * c.disc.mask
+        z = kd.jacobi_inverse(STIFF) * bh
+        assert kd.diag(STIFF)[c.mesh.boundary == 0].min() > 0
+        assert bh @ z > 0 and z @ kd.apply(STIFF, z) < 0
+        c.op.set_option(_lib.BP_OPT_CG_FUSE, fuse)
+        c.op.set_coeff(torch.from_numpy(np.ascontiguousarray(kap)).cuda())
+        b = dev(bh)
+        x = torch.zeros_like(b)
+        lib = _lib.load()
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for fixed, maxit in ((0, 50), (1, 6)):
+            x.zero_()
+            st = _lib.PcgStats()
+            rc = lib.bp_pcg_solve(c.op._h, STIFF, ctypes.c_void_p(b.data_ptr()),
+                                  ctypes.c_void_p(x.data_ptr()), 1e-8, maxit, fixed,
+                                  ctypes.byref(st), stream)
+            torch.cuda.synchronize()
+            assert rc == _lib.BP_ERR_BREAKDOWN, (fixed, rc)
+            if not fixed:
+                assert st.iters == 0, st.iters
+                assert float(torch.abs(x).max()) == 0.0
+            else:
+                assert st.iters == maxit
+        # with the coefficient removed the solve converges
+        c.op.set_coeff(None)
+        _, st = c.op.pcg_solve(b, rtol=1e-10, maxit=500)
+        assert st["converged"]
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("fuse", [2, 1, 0])
 def test_pcg_converged_solution_config1(fuse):
     import scipy.sparse.linalg as spla
     from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
