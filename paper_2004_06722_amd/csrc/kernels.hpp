@@ -345,7 +345,9 @@ __device__ __forceinline__ void stiff_colloc_body(
         }
         if (mb >> k & 1u) {
           if (LOCAL || (own && interior_node<P1>(i, j, k)))
-            wc[gk[k]] = acc;  // element-local output, or a node of this element alone
+            // element-local output, or a node of this element alone (streamed:
+            // nothing reads it again in this launch)
+            __builtin_nontemporal_store(acc, wc + gk[k]);
           else
             atomic_add(wc + gk[k], acc);
         }
@@ -923,7 +925,7 @@ __device__ __forceinline__ void gl_body(
           if (live) wc[ec * N3 + ci + P1 * (cj + P1 * k)] = (mb >> k & 1u) ? wk[k] : T(0);
         } else if (mb >> k & 1u) {
           if (own && interior_node<P1>(ci, cj, k))
-            wc[gk[k]] = wk[k];  // a node of this element alone
+            __builtin_nontemporal_store(wk[k], wc + gk[k]);  // a node of this element alone
           else
             atomic_add(wc + gk[k], wk[k]);
         }
