@@ -304,23 +304,26 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
 #define BP_OPT_CG_VARIANT 3
 #define BP_CG_STANDARD 0
 #define BP_CG_SINGLE_REDUCTION 1
-/*   BP_OPT_CG_FUSE (2, default, 1 or 0): with the standard recurrences, FP64
- *     and at most 1024 partial rows (about 2.6e5 nodes):
- *     1: every work-group of the residual update computes alpha from the
- *     operator's partial sums and every work-group of the direction update
- *     computes beta and the convergence test from the residual update's,
- *     each in one fixed order (bit-identical in all work-groups): three
- *     launches per iteration instead of five (the mass on Gauss-Legendre
- *     points, which assembles by a gather in the residual update, keeps
- *     five).
- *     2: as 1, except for the collocated stiffness operator of one
- *     component up to p = 8: its launch forms the direction
- *     p_k = z_k + beta p_{k-1} at the nodes it gathers (beta and the
- *     stopping test from the vector kernel's partial sums, reduced in one
- *     fixed order by every work-group) and one vector kernel stores p_k and
- *     updates x and the residual: two launches per iteration. The iterates
- *     are those of the standard recurrences.
- *     0 always runs the five. */
+/*   BP_OPT_CG_FUSE (2, default, 1 or 0): fewer launches per iteration with
+ *     the standard recurrences in FP64, where the partial-sum tables are short
+ *     enough for every work-group to reduce them itself, each in one fixed
+ *     order (bit-identical in all work-groups):
+ *     1: at most 1024 partial rows (about 2.6e5 nodes): every work-group of
+ *     the residual update computes alpha from the operator's partial sums and
+ *     every work-group of the direction update computes beta and the
+ *     convergence test from the residual update's: three launches per
+ *     iteration instead of five (the mass on Gauss-Legendre points, which
+ *     assembles by a gather in the residual update, keeps five).
+ *     2: in addition, for the collocated stiffness operator of one component
+ *     up to p = 8, while (vector rows) x (operator work-groups) stays at
+ *     most 4M (about 8e5 nodes at p = 7; rows of 256 nodes up to 1024
+ *     rows, of 1024 nodes beyond): the
+ *     operator launch forms the direction p_k = z_k + beta p_{k-1} at the
+ *     nodes it gathers (beta and the stopping test from the vector kernel's
+ *     partial sums) and one vector kernel stores p_k and updates x and the
+ *     residual: two launches per iteration. Elsewhere as 1.
+ *     The iterates are those of the standard recurrences. 0 always runs the
+ *     five launches. */
 #define BP_OPT_CG_FUSE 5
 int bp_set_option(bp_op op, int option, int value);
 

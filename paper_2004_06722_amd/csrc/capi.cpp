@@ -306,8 +306,10 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
   // the start of `part`, the residual update's follow them
   const bool fused =
       op->cg_fuse > 0 && sizeof(T) == 8 && !mass_wl && !resume && cg_fused_fits(n, nb_apply);
-  // two launches per iteration where the operator forms p itself (PZIter)
-  const bool fused2 = fused && op->cg_fuse == 2 && apply_pz_supported(op, which);
+  // two launches per iteration where the operator forms p itself (PZIter);
+  // its shorter vector table lets it run on larger meshes than the three
+  const bool fused2 = op->cg_fuse == 2 && sizeof(T) == 8 && !mass_wl && !resume &&
+                      apply_pz_supported(op, which) && cg_fused2_fits(n, nb_apply);
   double *const part_r = part + nb_apply * nc;
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
@@ -316,7 +318,7 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
       if constexpr (sizeof(T) == 8) {
         if (fused2) {
           const int k = it + c;
-          const PZIter pz{r, part_r, vec_blocks(n), sc, k & 1, check ? 1 : 0, k == 0 ? 1 : 0};
+          const PZIter pz{r, part_r, rxp_rows(n), sc, k & 1, check ? 1 : 0, k == 0 ? 1 : 0};
           if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
           rc = launch_apply_pz(op, p, w, masked, part, done, pz, s);
           if (rc) return rc;

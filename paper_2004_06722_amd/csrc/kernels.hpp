@@ -104,7 +104,21 @@ struct RowPairSums {
       a0 += v[q][0];
       a1 += v[q][1];
     }
-    for (int64_t r = threadIdx.x + (int64_t)U * THREADS; r < nb; r += THREADS) {
+    int64_t r = threadIdx.x + (int64_t)U * THREADS;
+    for (; r + 3 * THREADS < nb; r += 4 * THREADS) {  // four rows' loads together
+      double b[4][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        b[q][0] = part[2 * (r + q * THREADS)];
+        b[q][1] = part[2 * (r + q * THREADS) + 1];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a0 += b[q][0];
+        a1 += b[q][1];
+      }
+    }
+    for (; r < nb; r += THREADS) {
       a0 += part[2 * r];
       a1 += part[2 * r + 1];
     }

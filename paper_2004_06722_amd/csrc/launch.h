@@ -95,13 +95,22 @@ void cg_update_xp_fused(int nc, int64_t n, double *x, double *p, const double *z
                         const double *pr, DevScalars *sc, int parity, hipStream_t s,
                         bool check);
 
-// The two-launch iteration of small meshes (FP64, collocated stiffness, one
-// component, p1 <= 9; PZIter): the operator launch forms p_k = z_k + beta p_{k-1} while
-// gathering and takes the stopping test on r_k; cg_update_rxp_fused then
+// The two-launch iteration of small and mid-size meshes (FP64, collocated
+// stiffness, one component, p1 <= 9; PZIter; cg_fused2_fits): the operator
+// launch forms p_k = z_k + beta p_{k-1} while gathering and takes the
+// stopping test on r_k; cg_update_rxp_fused then
 // stores p_k, updates x and z = dinv r and writes the partials of the next
 // r.z and r.r into pr. cg_fin_rxp_fused, once after the last iteration,
 // reduces pr into the scalars the host reads (r.z, r.r, and the stopping
 // test of the last iterate).
+// k_cg_update_rxp_fused: one node per thread up to kFusedRows groups,
+// kRxpNodes beyond; the bounds of the two partial tables (measured at p = 7:
+// the two-launch form gains 13-14% at E = 2^10, 2^11 and breaks even at 2^12)
+constexpr int kRxpNodes = 4;
+constexpr int64_t kFused2VecRows = 2048, kFused2ApplyRows = 8192;
+constexpr int64_t kFused2Product = int64_t(4) << 20;
+int64_t rxp_rows(int64_t n);  // partial rows of the vector kernel
+bool cg_fused2_fits(int64_t n, int64_t nb_apply);
 bool apply_pz_supported(const bp_op_s *op, int which);
 int launch_apply_pz(const bp_op_s *op, const double *p, double *w, bool masked, double *part,
                     const int *done, const PZIter &pz, hipStream_t s);

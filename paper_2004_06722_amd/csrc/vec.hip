@@ -504,7 +504,21 @@ __device__ __forceinline__ void block_reduce_rows(const double *__restrict__ par
   double acc[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) acc[c] = 0.0;
-  for (int64_t r = threadIdx.x; r < nb; r += kVecThreads)
+  // rows t, t + 256, ... added in turn; the loads of four of them issued together
+  constexpr int U = W <= 4 ? 4 : 2;
+  int64_t r = threadIdx.x;
+  for (; r + (U - 1) * kVecThreads < nb; r += U * kVecThreads) {
+    double v[U][W];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) v[q][c] = part[(r + q * kVecThreads) * W + c];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] += v[q][c];
+  }
+  for (; r < nb; r += kVecThreads)
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] += part[r * W + c];
 #pragma unroll
@@ -650,26 +664,36 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_xp_fused(
 // initialisation). alpha from the operator's partials pa[nba][NC]; per node
 // p_k (stored), x += alpha p_k, z_{k+1} = z_k - alpha dinv w_k, w zeroed at
 // the nodes the operator adds into (v >= n_own); partials of r_{k+1}.z_{k+1}
-// and r_{k+1}.r_{k+1} into pr for the next operator launch. A breakdown or a
-// non-finite p.Ap ends the solve as in k_cg_update_r_fused.
-template <int NC>
+// and r_{k+1}.r_{k+1} into pr for the next operator launch, one row per
+// K * 256 nodes (thread t takes nodes t, t + 256, ... of its group, added
+// in that order): K = 1 on small meshes (more work-groups), kRxpNodes above
+// 1024 rows, so that the table that every work-group of the operator reduces
+// stays short. A breakdown or a non-finite p.Ap ends the
+// solve as in k_cg_update_r_fused.
+template <int NC, int K>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update_rxp_fused(
     int64_t n, double *__restrict__ x, double *__restrict__ p, double *__restrict__ z,
     double *__restrict__ w, const double *__restrict__ dinv, const double *__restrict__ pa,
     int64_t nba, double *__restrict__ pr, DevScalars *sc, int parity, int check, int first,
     int64_t n_own) {
   if (check && sc->done) return;  // x_k met the stopping test in the operator launch
-  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-  const bool in = v < n;
-  double di = 0.0, zo[NC], wo[NC], po[NC], xo[NC];
-  if (in) {  // requested before the reduction
-    di = dinv[v];
+  const int64_t v0 = (int64_t)blockIdx.x * (K * kVecThreads) + threadIdx.x;
+  double di[K], zo[K][NC], wo[K][NC], po[K][NC], xo[K][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      zo[c] = z[c * n + v];
-      wo[c] = w[c * n + v];
-      po[c] = p[c * n + v];
-      xo[c] = x[c * n + v];
+  for (int j = 0; j < K; ++j) {  // requested before the reduction
+    const int64_t v = v0 + j * kVecThreads;
+    di[j] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) zo[j][c] = wo[j][c] = po[j][c] = xo[j][c] = 0.0;
+    if (v < n) {
+      di[j] = dinv[v];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        zo[j][c] = z[c * n + v];
+        wo[j][c] = w[c * n + v];
+        po[j][c] = p[c * n + v];
+        xo[j][c] = x[c * n + v];
+      }
     }
   }
   __shared__ double pap[NC];
@@ -701,18 +725,21 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_rxp_fused(
   double acc[2 * NC];
 #pragma unroll
   for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
-  if (in) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int64_t v = v0 + j * kVecThreads;
+    if (v >= n) continue;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double pk = first ? po[c] : __builtin_fma(be[c], po[c], zo[c]);
+      const double pk = first ? po[j][c] : __builtin_fma(be[c], po[j][c], zo[j][c]);
       if (!first) p[c * n + v] = pk;
-      x[c * n + v] = xo[c] + al[c] * pk;
-      const double zv = zo[c] - (al[c] * di) * wo[c];
+      x[c * n + v] = xo[j][c] + al[c] * pk;
+      const double zv = zo[j][c] - (al[c] * di[j]) * wo[j][c];
       z[c * n + v] = zv;
       if (v >= n_own) w[c * n + v] = 0.0;
-      const double rv = di != 0.0 ? zv / di : 0.0;
-      acc[c] = rv * zv;
-      acc[NC + c] = rv * rv;
+      const double rv = di[j] != 0.0 ? zv / di[j] : 0.0;
+      acc[c] += rv * zv;
+      acc[NC + c] += rv * rv;
     }
   }
   block_partials<2 * NC>(acc, pr);
@@ -1341,38 +1368,36 @@ void cg_update_rxp_fused(int nc, int64_t n, double *x, double *p, double *z, dou
                          const double *dinv, const double *pa, int64_t nba, double *pr,
                          DevScalars *sc, int parity, hipStream_t s, bool check, bool first,
                          int64_t n_own) {
-#define BP_RXP(NC)                                                                          \
-  hipLaunchKernelGGL((k_cg_update_rxp_fused<NC>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, \
-                     s, n, x, p, z, w, dinv, pa, nba, pr, sc, parity, check ? 1 : 0,         \
-                     first ? 1 : 0, n_own)
-  switch (nc) {
-    case 1: BP_RXP(1); break;
-    case 2: BP_RXP(2); break;
-    case 3: BP_RXP(3); break;
-    case 4: BP_RXP(4); break;
-    case 5: BP_RXP(5); break;
-    case 6: BP_RXP(6); break;
-    case 7: BP_RXP(7); break;
-    default: BP_RXP(kMaxComp); break;
-  }
-#undef BP_RXP
+  (void)nc;  // one component (apply_pz_supported)
+  if (vec_blocks(n) <= kFusedRows)
+    hipLaunchKernelGGL((k_cg_update_rxp_fused<1, 1>), dim3(rxp_rows(n)), dim3(kVecThreads), 0,
+                       s, n, x, p, z, w, dinv, pa, nba, pr, sc, parity, check ? 1 : 0,
+                       first ? 1 : 0, n_own);
+  else
+    hipLaunchKernelGGL((k_cg_update_rxp_fused<1, kRxpNodes>), dim3(rxp_rows(n)),
+                       dim3(kVecThreads), 0, s, n, x, p, z, w, dinv, pa, nba, pr, sc, parity,
+                       check ? 1 : 0, first ? 1 : 0, n_own);
 }
 
 void cg_fin_rxp_fused(int nc, int64_t n, const double *pr, DevScalars *sc, hipStream_t s) {
-  const int64_t nb = vec_blocks(n);
-#define BP_FIN(NC) \
-  hipLaunchKernelGGL((k_fin_rxp_fused<NC>), dim3(1), dim3(kFinThreads), 0, s, pr, nb, sc)
-  switch (nc) {
-    case 1: BP_FIN(1); break;
-    case 2: BP_FIN(2); break;
-    case 3: BP_FIN(3); break;
-    case 4: BP_FIN(4); break;
-    case 5: BP_FIN(5); break;
-    case 6: BP_FIN(6); break;
-    case 7: BP_FIN(7); break;
-    default: BP_FIN(kMaxComp); break;
-  }
-#undef BP_FIN
+  (void)nc;
+  hipLaunchKernelGGL((k_fin_rxp_fused<1>), dim3(1), dim3(kFinThreads), 0, s, pr, rxp_rows(n),
+                     sc);
+}
+
+int64_t rxp_rows(int64_t n) {
+  if (vec_blocks(n) <= kFusedRows) return vec_blocks(n);
+  const int64_t g = kRxpNodes * kVecThreads;
+  return (n + g - 1) / g;
+}
+
+// Every work-group of each launch reads the other launch's whole partial
+// table: the bound keeps those redundant reads (rows x work-groups) small
+// against what the two dropped launches cost.
+bool cg_fused2_fits(int64_t n, int64_t nb_apply) {
+  const int64_t nv = rxp_rows(n);
+  return nv <= kFused2VecRows && nb_apply <= kFused2ApplyRows &&
+         nv * nb_apply <= kFused2Product;
 }
 
 bool cg_fused_fits(int64_t n, int64_t nb_apply) {

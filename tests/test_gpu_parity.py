@@ -269,6 +269,31 @@ def test_pcg_iterates_match_oracle_config1():
         c.close()
 
 
+def test_two_launch_iteration_on_a_mid_size_mesh():
+    # E = 12^3 at p = 7 (n = 593k): the operator's launch reduces a vector
+    # table of 580 rows (more than the 8 rows per thread it requests first)
+    # and the vector kernel an operator table of 1728 rows (several unrolled
+    # batches); iterates against the oracle and against the five-launch form
+    from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
+    c = Case(5, 7, 12, 12, 12, seed=31)
+    try:
+        mask = 1 - c.mesh.boundary
+        b = c.vec(33) * mask
+        rec = []
+        pcg(lambda v: c.disc.apply(STIFF, v, masked=True), b,
+            c.disc.jacobi_inverse(STIFF, masked=True), maxit=3, fixed_iters=True, record=rec)
+        xs = {}
+        for fuse in (2, 0):
+            c.op.set_option(BP_OPT_CG_FUSE, fuse)
+            x, st = c.op.pcg_solve(dev(b), maxit=3, fixed_iters=True)
+            assert st["iters"] == 3
+            xs[fuse] = host(x)
+            assert rel(xs[fuse], rec[2]) <= TOL, (fuse, rel(xs[fuse], rec[2]))
+        assert rel(xs[2], xs[0]) <= 1e-13
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("fuse", [2, 1, 0])
 def test_indefinite_coefficient_reports_breakdown(fuse):
     # kappa = -2 at the quadrature points within 0.15 of the centre and 1
