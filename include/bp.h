@@ -321,7 +321,12 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
  *     operator launch forms the direction p_k = z_k + beta p_{k-1} at the
  *     nodes it gathers (beta and the stopping test from the vector kernel's
  *     partial sums) and one vector kernel stores p_k and updates x and the
- *     residual: two launches per iteration. Elsewhere as 1.
+ *     residual: two launches per iteration. Above those bounds, while a
+ *     vector stays below 64 MiB, the same operator takes beta from the
+ *     finisher of the previous iteration and the vector kernel sits between
+ *     the two finishers: four launches.
+ *     Other operators as 1.
+ *     3: as 2 with the four-launch form at every size (for tests).
  *     The iterates are those of the standard recurrences. 0 always runs the
  *     five launches. */
 #define BP_OPT_CG_FUSE 5

@@ -81,6 +81,7 @@ struct PZIter {
   int parity;  // k & 1
   int check;   // a stopping test is honoured (not fixed iterations)
   int first;   // k = 0: p_0 = z_0 is stored already; nothing to reduce
+  int fused;   // 1: reduce pr here (two launches); 0: beta from sc->beta (four)
 };
 
 }  // namespace bp
@@ -116,7 +117,7 @@ struct bp_op_s {
   bool time_apply = false;
   int mixed_mode = 0;  // BP_MIXED_RESTART or BP_MIXED_RELIABLE (bp_pcg_solve_mixed)
   int cg_variant = 0;  // BP_CG_STANDARD or BP_CG_SINGLE_REDUCTION (bp_pcg_solve)
-  int cg_fuse = 2;  // BP_OPT_CG_FUSE: the fused iteration on small meshes (0 off, 1, 2)
+  int cg_fuse = 2;  // BP_OPT_CG_FUSE: fewer launches per iteration (0 off, 1, 2, 3)
   double *sv = nullptr;  // s = A p of the single-reduction PCG (allocated when selected)
   // Gauss-Legendre operators: the gather map transposed (CSR over global
   // nodes: the element-local slots e p1^3 + l of node g are

@@ -310,6 +310,14 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
   // its shorter vector table lets it run on larger meshes than the three
   const bool fused2 = op->cg_fuse == 2 && sizeof(T) == 8 && !mass_wl && !resume &&
                       apply_pz_supported(op, which) && cg_fused2_fits(n, nb_apply);
+  // above those bounds the same operator with beta from the finisher and one
+  // vector pass for p, x and z: four launches instead of five, while the
+  // vectors stay below the streaming size (measured at p = 7: 0.3-2% faster
+  // at E = 2^12..2^14, 1.2% slower at E = 2^18, where the z gathered by the
+  // operator costs more than the z the vector pass no longer reads)
+  const bool fused4 = sizeof(T) == 8 && !mass_wl && !resume && apply_pz_supported(op, which) &&
+                      !fused2 &&
+                      (op->cg_fuse == 3 || (op->cg_fuse == 2 && !cg_streams(n)));
   double *const part_r = part + nb_apply * nc;
   while (it < maxit) {
     const int chunk = fixed ? maxit - it : std::min(poll, maxit - it);
@@ -318,13 +326,25 @@ int pcg_run(bp_op op, const CgWork &ws, int which, bool f32, const T *b, T *x, c
       if constexpr (sizeof(T) == 8) {
         if (fused2) {
           const int k = it + c;
-          const PZIter pz{r, part_r, rxp_rows(n), sc, k & 1, check ? 1 : 0, k == 0 ? 1 : 0};
+          const PZIter pz{r, part_r, rxp_rows(n), sc, k & 1, check ? 1 : 0, k == 0 ? 1 : 0, 1};
           if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
           rc = launch_apply_pz(op, p, w, masked, part, done, pz, s);
           if (rc) return rc;
           if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
           cg_update_rxp_fused(nc, n, x, p, r, w, dinv, part, nb_apply, part_r, sc, k & 1, s,
                               check, k == 0, stored_rows(op, which));
+          continue;
+        }
+        if (fused4) {
+          const int k = it + c;
+          const PZIter pz{r, nullptr, 0, sc, k & 1, check ? 1 : 0, k == 0 ? 1 : 0, 0};
+          if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed], s));
+          rc = launch_apply_pz(op, p, w, masked, part, done, pz, s);
+          if (rc) return rc;
+          if (tm) BP_HIP(hipEventRecord(op->apply_ev[2 * timed++ + 1], s));
+          cg_fin_alpha(nc, part, nb_apply, sc, s, check);
+          cg_update_rxp(n, x, p, r, w, dinv, part, sc, s, check, k == 0, stored_rows(op, which));
+          cg_fin_beta(nc, nb_vec, part, sc, s, check);
           continue;
         }
       }
@@ -1113,7 +1133,8 @@ int bp_set_option(bp_op op, int option, int value) {
     return BP_OK;
   }
   if (option == BP_OPT_CG_FUSE) {
-    if (value < 0 || value > 2) return set_error(BP_ERR_ARG, "bp_set_option: CG fuse 0, 1 or 2");
+    if (value < 0 || value > 3)
+      return set_error(BP_ERR_ARG, "bp_set_option: CG fuse 0, 1, 2 or 3");
     op->cg_fuse = value;
     return BP_OK;
   }

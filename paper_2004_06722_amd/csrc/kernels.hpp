@@ -195,14 +195,19 @@ __device__ __forceinline__ void stiff_colloc_body(
   RowPairSums<PL::THREADS> pzs;
   double pz_rzo = 0.0, pz_bb = 1.0, pz_tol2 = 0.0;
   int pz_fixed = 1;
+  double pz_beta = 0.0;
   if constexpr (PZ) {
     if (!pz.first) {
       const DevScalars *sc = pz.sc;
-      pz_rzo = sc->rzs[pz.parity ^ 1][0];
-      pz_bb = sc->bb[0];
-      pz_tol2 = sc->tol2;
-      pz_fixed = sc->fixed;
-      pzs.issue(pz.pr, pz.nbv);
+      if (pz.fused) {
+        pz_rzo = sc->rzs[pz.parity ^ 1][0];
+        pz_bb = sc->bb[0];
+        pz_tol2 = sc->tol2;
+        pz_fixed = sc->fixed;
+        pzs.issue(pz.pr, pz.nbv);
+      } else {
+        pz_beta = sc->beta[0];  // from the finisher of the previous iteration
+      }
     }
   }
   // one round trip: the column of the gather map and of G
@@ -240,7 +245,6 @@ __device__ __forceinline__ void stiff_colloc_body(
   // launch in all of them at once; p_k = z_k + beta p_{k-1} at the nodes
   T pzp[PZ ? P1 : 1], pzz[PZ ? P1 : 1];
   __shared__ double pzr[2];
-  double pz_beta = 0.0;
   if constexpr (PZ) {
     static_assert(!MULTI, "the two-launch iteration runs one component");
 #pragma unroll
@@ -248,7 +252,7 @@ __device__ __forceinline__ void stiff_colloc_body(
       pzp[k] = u[gk[k]];
       pzz[k] = pz.first ? T(0) : pz.z[gk[k]];
     }
-    if (!pz.first) {
+    if (!pz.first && pz.fused) {
       pzs.finish(pz.pr, pz.nbv, pzr);
       const double bb = pz_bb > 0.0 ? pz_bb : 1.0;
       const bool conv = !pz_fixed && pzr[1] <= pz_tol2 * bb;
@@ -265,9 +269,10 @@ __device__ __forceinline__ void stiff_colloc_body(
         if (stop) sc->done = sc->halted = 1;  // x_k is the answer
       }
       if (stop) return;
+    }
+    if (!pz.first)
 #pragma unroll
       for (int k = 0; k < P1; ++k) pzp[k] = __builtin_fma(pz_beta, pzp[k], pzz[k]);
-    }
   }
 
   const int nrun = MULTI ? ncomp : 1;

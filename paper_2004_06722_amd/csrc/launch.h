@@ -119,6 +119,14 @@ void cg_update_rxp_fused(int nc, int64_t n, double *x, double *p, double *z, dou
                          DevScalars *sc, int parity, hipStream_t s, bool check, bool first,
                          int64_t n_own);
 void cg_fin_rxp_fused(int nc, int64_t n, const double *pr, DevScalars *sc, hipStream_t s);
+// The four-launch form (one component, above those bounds): the operator
+// launch (PZIter with fused = 0: beta from k_fin_beta), cg_fin_alpha,
+// cg_update_rxp (p, x and z in one pass; partials for cg_fin_beta),
+// cg_fin_beta.
+bool cg_streams(int64_t n);  // FP64 vectors of n entries take the streaming kernels
+void cg_update_rxp(int64_t n, double *x, double *p, double *z, double *w, const double *dinv,
+                   double *part, DevScalars *sc, hipStream_t s, bool check, bool first,
+                   int64_t n_own);
 
 // transposed gather Q^T w_L: w[c][g] += sum of wl[c][pos[k]] for k in
 // [off[g], off[g+1]) in ascending order (wl is [nc][nl]); skipped while

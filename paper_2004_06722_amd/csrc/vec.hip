@@ -745,6 +745,40 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update_rxp_fused(
   block_partials<2 * NC>(acc, pr);
 }
 
+// The vector kernel of the four-launch form (one component, meshes above the
+// two-launch bounds): the operator has applied A to p_k = z_k + beta p_{k-1}
+// with beta from k_fin_beta, and k_fin_alpha has formed alpha; per node p_k
+// (stored, the same fma as the operator's), x += alpha p_k, z_{k+1} =
+// z_k - alpha dinv w_k, w cleared on the nodes the operator adds into;
+// partials of r.z and r.r as k_cg_update_r writes them (for k_fin_beta).
+// Five words read and three written per node, against the six and four of
+// the residual and direction updates.
+template <bool NT>
+__global__ __launch_bounds__(kVecThreads) void k_cg_update_rxp(
+    int64_t n, double *__restrict__ x, double *__restrict__ p, double *__restrict__ z,
+    double *__restrict__ w, const double *__restrict__ dinv, double *__restrict__ part,
+    const DevScalars *__restrict__ sc, int check, int first, int64_t n_own) {
+  if (check && sc->done) return;
+  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const double al = sc->alpha[0], be = first ? 0.0 : sc->beta[0];
+  double rz = 0.0, rr = 0.0;
+  if (v < n) {
+    const double di = ld_v<NT>(dinv + v), zo = ld_v<NT>(z + v), wo = ld_v<NT>(w + v);
+    const double po = ld_v<NT>(p + v), xo = ld_v<NT>(x + v);
+    const double pk = first ? po : __builtin_fma(be, po, zo);
+    if (!first) st_v<NT>(p + v, pk);
+    st_v<NT>(x + v, xo + al * pk);
+    const double zv = zo - (al * di) * wo;
+    st_v<NT>(z + v, zv);
+    if (v >= n_own) st_v<NT>(w + v, 0.0);
+    const double rv = di != 0.0 ? zv / di : 0.0;
+    rz = rv * zv;
+    rr = rv * rv;
+  }
+  block_partial1(rz, part, 2, 0);
+  block_partial1(rr, part, 2, 1);
+}
+
 // After the last iteration of the two-launch form: r.z and r.r of the last
 // iterate from the partials pr, and its stopping test. Nothing to do once
 // the solve halted (a stopping test met in an operator launch, which stored
@@ -1384,6 +1418,19 @@ void cg_fin_rxp_fused(int nc, int64_t n, const double *pr, DevScalars *sc, hipSt
   hipLaunchKernelGGL((k_fin_rxp_fused<1>), dim3(1), dim3(kFinThreads), 0, s, pr, rxp_rows(n),
                      sc);
 }
+
+void cg_update_rxp(int64_t n, double *x, double *p, double *z, double *w, const double *dinv,
+                   double *part, DevScalars *sc, hipStream_t s, bool check, bool first,
+                   int64_t n_own) {
+  if (n * (int64_t)sizeof(double) >= kStreamBytes)
+    hipLaunchKernelGGL((k_cg_update_rxp<true>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, n,
+                       x, p, z, w, dinv, part, sc, check ? 1 : 0, first ? 1 : 0, n_own);
+  else
+    hipLaunchKernelGGL((k_cg_update_rxp<false>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, s,
+                       n, x, p, z, w, dinv, part, sc, check ? 1 : 0, first ? 1 : 0, n_own);
+}
+
+bool cg_streams(int64_t n) { return n * (int64_t)sizeof(double) >= kStreamBytes; }
 
 int64_t rxp_rows(int64_t n) {
   if (vec_blocks(n) <= kFusedRows) return vec_blocks(n);

@@ -170,7 +170,7 @@ def manufactured_rhs(c):
     return c.disc.apply(MASS, f, masked=False) * c.disc.mask
 
 
-@pytest.mark.parametrize("fuse", [2, 1, 0])
+@pytest.mark.parametrize("fuse", [3, 2, 1, 0])
 @pytest.mark.parametrize("bp,p,ncomp", [(5, 1, 1), (5, 2, 1), (5, 4, 1), (5, 5, 1), (5, 6, 2),
                                          (5, 7, 1), (5, 7, 3), (5, 8, 2), (5, 5, 8), (3, 4, 1),
                                          (3, 6, 1), (1, 5, 1)])
@@ -180,7 +180,8 @@ def test_pcg_iterates_match_oracle_orders(bp, p, ncomp, fuse):
     # fuse 1 the vector updates compute alpha and beta themselves (small
     # meshes), with fuse 2 the collocated stiffness operator of one component
     # also forms the direction p = z + beta p while it gathers (two launches
-    # per iteration; several components keep the three-launch form)
+    # per iteration; several components keep the three-launch form), with
+    # fuse 3 it takes beta from the finisher (four launches)
     from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
     c = Case(bp, p, *grid_for(p), seed=21, ncomp=ncomp)
     try:
@@ -283,18 +284,18 @@ def test_two_launch_iteration_on_a_mid_size_mesh():
         pcg(lambda v: c.disc.apply(STIFF, v, masked=True), b,
             c.disc.jacobi_inverse(STIFF, masked=True), maxit=3, fixed_iters=True, record=rec)
         xs = {}
-        for fuse in (2, 0):
+        for fuse in (2, 3, 0):
             c.op.set_option(BP_OPT_CG_FUSE, fuse)
             x, st = c.op.pcg_solve(dev(b), maxit=3, fixed_iters=True)
             assert st["iters"] == 3
             xs[fuse] = host(x)
             assert rel(xs[fuse], rec[2]) <= TOL, (fuse, rel(xs[fuse], rec[2]))
-        assert rel(xs[2], xs[0]) <= 1e-13
+        assert rel(xs[2], xs[0]) <= 1e-13 and rel(xs[3], xs[0]) <= 1e-13
     finally:
         c.close()
 
 
-@pytest.mark.parametrize("fuse", [2, 1, 0])
+@pytest.mark.parametrize("fuse", [3, 2, 1, 0])
 def test_indefinite_coefficient_reports_breakdown(fuse):
     # kappa = -2 at the quadrature points within 0.15 of the centre and 1
     # elsewhere makes the BP5 stiffness indefinite while its diagonal stays
@@ -345,7 +346,7 @@ def test_indefinite_coefficient_reports_breakdown(fuse):
         c.close()
 
 
-@pytest.mark.parametrize("fuse", [2, 1, 0])
+@pytest.mark.parametrize("fuse", [3, 2, 1, 0])
 def test_pcg_converged_solution_config1(fuse):
     import scipy.sparse.linalg as spla
     from paper_2004_06722_amd._lib import BP_OPT_CG_FUSE
