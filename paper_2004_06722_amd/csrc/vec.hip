@@ -144,7 +144,10 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
 // The iteration kernels give an FP32 thread two nodes of its group's 256
 // (v and v + 128, 128 threads): a wave then has as many bytes in flight as
 // an FP64 wave with one node per thread, and the partial tables keep one row
-// per 256 nodes whatever the precision.
+// per 256 nodes whatever the precision. The residual and direction updates
+// of one component take two nodes per thread in FP64 too (their template
+// parameter K; 2% faster at 9e7 nodes); kNodesPerThread is the choice of the
+// other kernels.
 template <typename T>
 constexpr int kNodesPerThread = sizeof(T) == 4 ? 2 : 1;
 template <typename T>
@@ -266,11 +269,11 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_alpha(const double *__restr
 // Nodes below n_own are element-interior nodes in the internal order (see
 // interior_first_order): the operator overwrites their w with plain stores,
 // so w is cleared only from n_own on (likewise in k_sr_update).
-template <typename T, bool NT>
-__global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r(
+template <typename T, bool NT, int K>
+__global__ __launch_bounds__(kVecThreads / K) void k_cg_update_r(
     int64_t n, T *__restrict__ z, T *__restrict__ w, const T *__restrict__ dinv,
     double *__restrict__ part, const DevScalars *__restrict__ sc, int check, int64_t n_own) {
-  constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
+  constexpr int TH = kVecThreads / K;
   if (check && sc->done) return;
   const int comp = blockIdx.y, nc = gridDim.y;
   const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
@@ -837,13 +840,13 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_beta(const double *__restri
 // the iteration just converged. `halted` (set by the next k_fin_alpha once
 // done is seen) stops the x update in the launches queued after the last
 // iteration.
-template <typename T, bool NT>
-__global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_xp(int64_t n, T *__restrict__ x,
-                                                                  T *__restrict__ p,
-                                                                  const T *__restrict__ z,
-                                                                  const DevScalars *__restrict__ sc,
-                                                                  int check) {
-  constexpr int K = kNodesPerThread<T>, TH = kGroupThreads<T>;
+template <typename T, bool NT, int K>
+__global__ __launch_bounds__(kVecThreads / K) void k_cg_update_xp(int64_t n, T *__restrict__ x,
+                                                                 T *__restrict__ p,
+                                                                 const T *__restrict__ z,
+                                                                 const DevScalars *__restrict__ sc,
+                                                                 int check) {
+  constexpr int TH = kVecThreads / K;
   if (check && sc->halted) return;
   const int comp = blockIdx.y;
   const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
@@ -1348,14 +1351,14 @@ void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, Dev
       update_r_nc<T, false>(nc, n, r, w, dinv, part, sc, s, check ? 1 : 0, n_own);
     return;
   }
+  // one component: two nodes per thread in either precision
+  constexpr int K = 2;
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
-    hipLaunchKernelGGL((k_cg_update_r<T, true>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0,
-                       n_own);
+    hipLaunchKernelGGL((k_cg_update_r<T, true, K>), dim3(vec_blocks(n), nc),
+                       dim3(kVecThreads / K), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0, n_own);
   else
-    hipLaunchKernelGGL((k_cg_update_r<T, false>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0,
-                       n_own);
+    hipLaunchKernelGGL((k_cg_update_r<T, false, K>), dim3(vec_blocks(n), nc),
+                       dim3(kVecThreads / K), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0, n_own);
 }
 
 void cg_fin_beta(int nc, int64_t nb, const double *part, DevScalars *sc, hipStream_t s,
@@ -1468,12 +1471,28 @@ void cg_update_xp_fused(int nc, int64_t n, double *x, double *p, const double *z
 template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
                   bool check) {
-  if (n * (int64_t)sizeof(T) >= kStreamBytes)
-    hipLaunchKernelGGL((k_cg_update_xp<T, true>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, x, p, z, sc, check ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_cg_update_xp<T, false>), dim3(vec_blocks(n), nc),
-                       dim3(kGroupThreads<T>), 0, s, n, x, p, z, sc, check ? 1 : 0);
+  // two nodes per thread, except FP64 with several components (measured: the
+  // one-component FP64 updates 2% faster with two, the three-component ones
+  // 1-2% slower)
+  const bool two = sizeof(T) == 4 || nc == 1;
+  const bool nt = n * (int64_t)sizeof(T) >= kStreamBytes;
+  const dim3 g(vec_blocks(n), nc);
+  const int c = check ? 1 : 0;
+  if (two) {
+    if (nt)
+      hipLaunchKernelGGL((k_cg_update_xp<T, true, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p,
+                         z, sc, c);
+    else
+      hipLaunchKernelGGL((k_cg_update_xp<T, false, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p,
+                         z, sc, c);
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((k_cg_update_xp<T, true, 1>), g, dim3(kVecThreads), 0, s, n, x, p, z,
+                         sc, c);
+    else
+      hipLaunchKernelGGL((k_cg_update_xp<T, false, 1>), g, dim3(kVecThreads), 0, s, n, x, p, z,
+                         sc, c);
+  }
 }
 
 template <typename T>
