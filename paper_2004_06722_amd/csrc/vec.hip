@@ -145,9 +145,9 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
 // (v and v + 128, 128 threads): a wave then has as many bytes in flight as
 // an FP64 wave with one node per thread, and the partial tables keep one row
 // per 256 nodes whatever the precision. The residual and direction updates
-// of one component take two nodes per thread in FP64 too (their template
-// parameter K; 2% faster at 9e7 nodes); kNodesPerThread is the choice of the
-// other kernels.
+// of one component take two FP64 or four FP32 nodes per thread (their
+// template parameter K; each 2% faster than one and two); kNodesPerThread is
+// the choice of the other kernels.
 template <typename T>
 constexpr int kNodesPerThread = sizeof(T) == 4 ? 2 : 1;
 template <typename T>
@@ -1351,8 +1351,8 @@ void cg_update_r(int nc, int64_t n, T *r, T *w, const T *dinv, double *part, Dev
       update_r_nc<T, false>(nc, n, r, w, dinv, part, sc, s, check ? 1 : 0, n_own);
     return;
   }
-  // one component: two nodes per thread in either precision
-  constexpr int K = 2;
+  // one component: two FP64 or four FP32 nodes per thread
+  constexpr int K = sizeof(T) == 4 ? 4 : 2;
   if (n * (int64_t)sizeof(T) >= kStreamBytes)
     hipLaunchKernelGGL((k_cg_update_r<T, true, K>), dim3(vec_blocks(n), nc),
                        dim3(kVecThreads / K), 0, s, n, r, w, dinv, part, sc, check ? 1 : 0, n_own);
@@ -1478,7 +1478,14 @@ void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hip
   const bool nt = n * (int64_t)sizeof(T) >= kStreamBytes;
   const dim3 g(vec_blocks(n), nc);
   const int c = check ? 1 : 0;
-  if (two) {
+  if (sizeof(T) == 4 && nc == 1) {  // one FP32 component: four nodes per thread
+    if (nt)
+      hipLaunchKernelGGL((k_cg_update_xp<T, true, 4>), g, dim3(kVecThreads / 4), 0, s, n, x, p,
+                         z, sc, c);
+    else
+      hipLaunchKernelGGL((k_cg_update_xp<T, false, 4>), g, dim3(kVecThreads / 4), 0, s, n, x, p,
+                         z, sc, c);
+  } else if (two) {
     if (nt)
       hipLaunchKernelGGL((k_cg_update_xp<T, true, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p,
                          z, sc, c);
