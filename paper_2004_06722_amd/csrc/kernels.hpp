@@ -507,8 +507,11 @@ __global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_mass_colloc(
 // The quadrature data of these operators (G, B~) are stored with the point
 // index reversed, [a][b][c] with c fastest, so that the stage-3 pencils,
 // adjacent lanes along (b, c), read them coalesced; G and the gather map are
-// requested at entry. One component per launch (u and w point at component
-// c0). With LOCAL the input is read and the result stored per element. With
+// requested at entry. k_op_gl applies one component (u and w point at
+// component c0); k_op_gl_nc all of them, G and the map loaded once per
+// element (the multi-component stiffness stages its point values through
+// LDS and requests the next component's gather during stage 4). With LOCAL
+// the input is read and the result stored per element. With
 // WL the input is gathered from the global vector and the element result
 // w_L is stored per element ([E][p1^3], zero at skipped nodes) instead of
 // scatter-added: the mass operator moves little quadrature data, so FP64
