@@ -52,8 +52,10 @@ constexpr int kMaxTimedApplies = 4096;
 struct DevScalars {
   double rz[kMaxComp], pap[kMaxComp], rr[kMaxComp], bb[kMaxComp];
   double rzp[kMaxComp];  // r.z before the last update (used after a residual replacement)
-  // r.z by iteration parity for the fused small-mesh iteration: iteration k
-  // reads rzs[k & 1] and its direction update writes rzs[(k + 1) & 1]
+  // r.z by iteration parity for the fused small-mesh iterations: in the
+  // three-launch form iteration k reads rzs[k & 1] and its direction update
+  // writes rzs[(k + 1) & 1]; in the two-launch form (PZIter) the operator
+  // launch of iteration k writes rzs[k & 1] and reads rzs[(k - 1) & 1]
   double rzs[2][kMaxComp];
   double alpha[kMaxComp], beta[kMaxComp];
   double tol2;
