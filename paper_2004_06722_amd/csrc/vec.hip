@@ -146,12 +146,31 @@ __global__ __launch_bounds__(kVecThreads) void k_fill(T *x, int64_t n, T v) {
 // an FP64 wave with one node per thread, and the partial tables keep one row
 // per 256 nodes whatever the precision. The residual and direction updates
 // of one component take two FP64 or four FP32 nodes per thread (their
-// template parameter K; each 2% faster than one and two); kNodesPerThread is
-// the choice of the other kernels.
+// template parameter K; each 2% faster than one and two), those of several
+// components two (the residual update up to four components);
+// kNodesPerThread is the choice of the other kernels.
 template <typename T>
 constexpr int kNodesPerThread = sizeof(T) == 4 ? 2 : 1;
 template <typename T>
 constexpr int kGroupThreads = kVecThreads / kNodesPerThread<T>;
+// Component c of a component-major vector starts (c n) mod 64 entries past a
+// 64-entry boundary, so for n not a multiple of 64 a wave's 64 consecutive
+// nodes of c > 0 straddle one more cache line than those of component 0
+// (five 128-byte lines instead of four in FP64; measured on the
+// three-component direction update at n = 337^3: 785 us against 718 us
+// when realigned). The multi-component updates therefore shift the nodes of
+// component c back by head = (c n) mod 64: slot s of the grid's span
+// (gridDim.x * 256 >= n slots) takes node s - head, and the first head slots
+// wrap round to the end of the span, so every node is still taken exactly
+// once and the partial tables keep their rows.
+__device__ __forceinline__ int64_t comp_head(int c, int64_t n) {
+  return c ? ((int64_t)c * n) & 63 : 0;
+}
+__device__ __forceinline__ int64_t comp_node(int64_t slot, int64_t head) {
+  const int64_t v = slot - head;
+  return v < 0 ? v + (int64_t)gridDim.x * kVecThreads : v;
+}
+
 template <int TH = kVecThreads>
 __device__ __forceinline__ void block_partial1(double v, double *part, int width, int col) {
   constexpr int NW = TH / 64;
@@ -385,9 +404,9 @@ __global__ __launch_bounds__(kGroupThreads<T>) void k_cg_update_r_gather(
 // Partial sums of W values over the work-group in a fixed order: row
 // blockIdx.x of part[.][W] (one shuffle tree per wave, then the wave sums in
 // order; one barrier for all W).
-template <int W>
+template <int W, int TH = kVecThreads>
 __device__ __forceinline__ void block_partials(double (&v)[W], double *part) {
-  constexpr int NW = kVecThreads / 64;
+  constexpr int NW = TH / 64;
   __shared__ double red[NW][W];
 #pragma unroll
   for (int c = 0; c < W; ++c) {
@@ -409,34 +428,50 @@ __device__ __forceinline__ void block_partials(double (&v)[W], double *part) {
 // of them, so dinv is read once per node (the component-per-row grid of
 // k_cg_update_r reads it once per component). Partial columns as there:
 // r.z of component c in column c, r.r in column NC + c.
-template <typename T, bool NT, int NC>
-__global__ __launch_bounds__(kVecThreads) void k_cg_update_r_nc(
+template <typename T, bool NT, int NC, int K>
+__global__ __launch_bounds__(kVecThreads / K) void k_cg_update_r_nc(
     int64_t n, T *__restrict__ z, T *__restrict__ w, const T *__restrict__ dinv,
     double *__restrict__ part, const DevScalars *__restrict__ sc, int check, int64_t n_own) {
+  constexpr int TH = kVecThreads / K;
   if (check && sc->done) return;
-  const int64_t v = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
   double acc[2 * NC];
 #pragma unroll
   for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
-  if (v < n) {
-    const T di = ld_v<NT>(dinv + v);
-    T zo[NC], wo[NC];
+  // component c takes node vc (shifted by comp_head); the nodes of one group
+  // differ by less than 64 between components, so the extra dinv loads fall
+  // on the cache lines component 0 brings in
+  int64_t vc[K][NC];
+  T di[K][NC], zo[K][NC], wo[K][NC];
+#pragma unroll
+  for (int j = 0; j < K; ++j)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      zo[c] = ld_v<NT>(z + c * n + v);
-      wo[c] = ld_v<NT>(w + c * n + v);
+      const int64_t v = vc[j][c] = comp_node(s0 + j * TH, comp_head(c, n));
+      di[j][c] = zo[j][c] = wo[j][c] = T(0);
+      if (v < n) {
+        di[j][c] = ld_v<NT>(dinv + v);
+        zo[j][c] = ld_v<NT>(z + c * n + v);
+        wo[j][c] = ld_v<NT>(w + c * n + v);
+      }
     }
 #pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const T zv = zo[c] - ((T)sc->alpha[c] * di) * wo[c];
-      st_v<NT>(z + c * n + v, zv);
-      if (v >= n_own) st_v<NT>(w + c * n + v, T(0));
-      const T rv = di != T(0) ? zv / di : T(0);
-      acc[c] = (double)rv * (double)zv;
-      acc[NC + c] = (double)rv * (double)rv;
+      const int64_t v = vc[j][c];
+      if (v < n) {
+        const int64_t f = c * n + v;
+        const T d = di[j][c];
+        const T zv = zo[j][c] - ((T)sc->alpha[c] * d) * wo[j][c];
+        st_v<NT>(z + f, zv);
+        if (v >= n_own) st_v<NT>(w + f, T(0));
+        const T rv = d != T(0) ? zv / d : T(0);
+        acc[c] += (double)rv * (double)zv;
+        acc[NC + c] += (double)rv * (double)rv;
+      }
     }
-  }
-  block_partials<2 * NC>(acc, part);
+  block_partials<2 * NC, TH>(acc, part);
 }
 
 // k_cg_update_r_gather for NC > 1 components: the node's offsets and slot
@@ -849,14 +884,15 @@ __global__ __launch_bounds__(kVecThreads / K) void k_cg_update_xp(int64_t n, T *
   constexpr int TH = kVecThreads / K;
   if (check && sc->halted) return;
   const int comp = blockIdx.y;
-  const int64_t v0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kVecThreads + threadIdx.x, head = comp_head(comp, n);
   const T al = (T)sc->alpha[comp], be = (T)sc->beta[comp];
   // z is loaded whether or not the direction is updated, so that its load
   // does not wait for the done flag; only the store of p depends on it
   T pv[K], xv[K], zv[K];
+  int64_t vj[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const int64_t v = v0 + j * TH;
+    const int64_t v = vj[j] = comp_node(s0 + j * TH, head);
     pv[j] = xv[j] = zv[j] = T(0);
     if (v < n) {
       pv[j] = ld_v<NT>(p + comp * n + v);
@@ -867,7 +903,7 @@ __global__ __launch_bounds__(kVecThreads / K) void k_cg_update_xp(int64_t n, T *
   const bool dir = !sc->done;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const int64_t v = v0 + j * TH;
+    const int64_t v = vj[j];
     if (v < n) {
       const int64_t f = comp * n + v;
       st_v<NT>(x + f, xv[j] + al * pv[j]);
@@ -1323,8 +1359,11 @@ void cg_fin_alpha(int nc, const double *part, int64_t nb, DevScalars *sc, hipStr
 template <typename T, bool NT, int NC>
 static void launch_update_r_nc(int64_t n, T *r, T *w, const T *dinv, double *part,
                                DevScalars *sc, hipStream_t s, int check, int64_t n_own) {
-  hipLaunchKernelGGL((k_cg_update_r_nc<T, NT, NC>), dim3(vec_blocks(n)), dim3(kVecThreads), 0, s,
-                     n, r, w, dinv, part, sc, check, n_own);
+  // two nodes per thread up to four components (measured on three at
+  // n = 337^3: 567 us against 573 us with one)
+  constexpr int K = NC <= 4 ? 2 : 1;
+  hipLaunchKernelGGL((k_cg_update_r_nc<T, NT, NC, K>), dim3(vec_blocks(n)), dim3(kVecThreads / K),
+                     0, s, n, r, w, dinv, part, sc, check, n_own);
 }
 
 template <typename T, bool NT>
@@ -1471,10 +1510,10 @@ void cg_update_xp_fused(int nc, int64_t n, double *x, double *p, const double *z
 template <typename T>
 void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hipStream_t s,
                   bool check) {
-  // two nodes per thread, except FP64 with several components (measured: the
-  // one-component FP64 updates 2% faster with two, the three-component ones
-  // 1-2% slower)
-  const bool two = sizeof(T) == 4 || nc == 1;
+  // two nodes per thread, four for one FP32 component (measured: the
+  // one-component FP64 update 2% faster with two than with one; the
+  // three-component one, with its components realigned by comp_head, 692 us
+  // against 767 us with one at n = 337^3)
   const bool nt = n * (int64_t)sizeof(T) >= kStreamBytes;
   const dim3 g(vec_blocks(n), nc);
   const int c = check ? 1 : 0;
@@ -1485,20 +1524,12 @@ void cg_update_xp(int nc, int64_t n, T *x, T *p, const T *z, DevScalars *sc, hip
     else
       hipLaunchKernelGGL((k_cg_update_xp<T, false, 4>), g, dim3(kVecThreads / 4), 0, s, n, x, p,
                          z, sc, c);
-  } else if (two) {
-    if (nt)
-      hipLaunchKernelGGL((k_cg_update_xp<T, true, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p,
-                         z, sc, c);
-    else
-      hipLaunchKernelGGL((k_cg_update_xp<T, false, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p,
-                         z, sc, c);
+  } else if (nt) {
+    hipLaunchKernelGGL((k_cg_update_xp<T, true, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p, z,
+                       sc, c);
   } else {
-    if (nt)
-      hipLaunchKernelGGL((k_cg_update_xp<T, true, 1>), g, dim3(kVecThreads), 0, s, n, x, p, z,
-                         sc, c);
-    else
-      hipLaunchKernelGGL((k_cg_update_xp<T, false, 1>), g, dim3(kVecThreads), 0, s, n, x, p, z,
-                         sc, c);
+    hipLaunchKernelGGL((k_cg_update_xp<T, false, 2>), g, dim3(kVecThreads / 2), 0, s, n, x, p, z,
+                       sc, c);
   }
 }
 
