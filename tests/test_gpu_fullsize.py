@@ -76,6 +76,35 @@ def test_bp6_n7_e48cube_vector_sampled():
     op.close()
 
 
+def test_bp6_n7_e48cube_pcg_components_match_scalar_solves():
+    # the vector benchmark's path at its size: n = 337^3 is not a multiple of
+    # 64, so components 1 and 2 start inside a 64-node group and the
+    # three-component updates shift their nodes (streamed vectors, two nodes
+    # per thread); each component of the vector solve must equal the
+    # one-component solve of its right-hand side on the same mesh
+    op3, mesh, _, dirich = build(6, 7, (48, 48, 48), ncomp=3)
+    op1 = None
+    try:
+        n = mesh.nglobal
+        assert n % 64 != 0 and (2 * n) % 64 != 0
+        b = torch.from_numpy(np.ascontiguousarray(
+            synth.rhs_uniform(n, 21, ncomp=3, dirichlet=dirich).T)).cuda()
+        for k in (1, 5):
+            x3, _ = op3.pcg_solve(b, maxit=k, fixed_iters=True)
+            xs = x3.cpu().numpy()
+            if op1 is None:  # BP5 on the same mesh
+                import paper_2004_06722_amd.bp as B
+                q, quad = B.bp_quadrature(5, 7)
+                op1 = B.Operator(7, q, quad, mesh.elem_dofs, mesh.node_xyz, n, dirich)
+            for c in range(3):
+                x1, _ = op1.pcg_solve(b[c].contiguous(), maxit=k, fixed_iters=True)
+                assert rel(xs[c], x1.cpu().numpy()) <= TOL, (k, c)
+    finally:
+        op3.close()
+        if op1 is not None:
+            op1.close()
+
+
 @pytest.mark.parametrize("bp,N,k", [(3, 7, 15), (1, 7, 15), (3, 3, 18), (1, 2, 20)])
 def test_bp1_bp3_sampled(bp, N, k):
     op, _ = sampled_check(bp, N, k, which=MASS if bp == 1 else STIFF)
