@@ -275,6 +275,24 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g,
                   void *stream);
 
 /*
+ * bp_mass_misfit -- the data misfit of the variable-coefficient problem and
+ * its gradient: L = 1/2 sum_c d_c^T M d_c and dL/du = M d, with d = u -
+ * u_target and M = Q^T B_L Q the unmasked mass matrix of the operator's own
+ * quadrature (section 5 eq. (mass); M is symmetric). With bp_pcg_solve and
+ * bp_grad_kappa it gives the adjoint gradient of L with respect to the
+ * coefficient of bp_set_coeff (A lam = mask * M d, then bp_grad_kappa).
+ * d^T M d is summed from the element energies d_L^T B_L d_L in a fixed
+ * order, so repeated calls give the same bits.
+ *   u, u_target: device double [ncomp][nglobal], read only.
+ *   grad: device double [ncomp][nglobal], overwritten with M d; NULL skips it.
+ *   loss: host double, written on return (the call synchronises the stream).
+ * Errors: BP_ERR_ARG (NULL u, u_target or loss; grad aliasing an input),
+ * BP_ERR_HIP.
+ */
+int bp_mass_misfit(bp_op op, const double *u, const double *u_target, double *grad,
+                   double *loss, void *stream);
+
+/*
  * bp_set_option -- operator options (host state only, no device work).
  *   BP_OPT_TIME_APPLY (value 0/1): bp_pcg_solve records a HIP event pair on
  *   its stream around every operator launch of the iteration loop (at most

@@ -62,6 +62,7 @@ SIGNATURES = {
     "bp_pcg_solve_static": (_i, [_vp, _i, _vp, _vp, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),
     "bp_pcg_solve_mixed": (_i, [_vp, _vp, _vp, _d, _d, _i, _i, ctypes.POINTER(PcgStats), _vp]),
     "bp_grad_kappa": (_i, [_vp, _vp, _vp, _vp, _vp]),
+    "bp_mass_misfit": (_i, [_vp, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]),
     "bp_set_option": (_i, [_vp, _i, _i]),
     "bp_destroy": (_i, [_vp]),
     "bp_last_error": (ctypes.c_char_p, []),

@@ -9,14 +9,16 @@ returns
     dL/dkappa_q = - sum_c (D lambda_c)_q^T G_q (D u_c)_q   (bp_grad_kappa)
     dL/db       = lambda.
 
-Both solves and the gradient kernel run in libbp.so; torch only holds the
-tensors and records the graph.
+The misfit L = 1/2 sum_c (u - u_t)_c^T M (u - u_t)_c and its gradient M (u - u_t)
+come from bp_mass_misfit. Both solves, the gradient kernel and the misfit run
+in libbp.so; torch only holds the tensors, records the graph and scales the
+returned gradients by the incoming one (the chain rule).
 """
 from __future__ import annotations
 
 import torch
 
-from .bp import MASS, Operator
+from .bp import Operator
 
 
 class PoissonSolve(torch.autograd.Function):
@@ -50,10 +52,10 @@ class MassNormLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u: torch.Tensor, u_target: torch.Tensor, op: Operator):
-        d = (u - u_target).detach().contiguous()
-        Md = op.apply(MASS, d, masked=False)
+        # the library forms d, M d and the sum (bp_mass_misfit)
+        loss, Md = op.mass_misfit(u.detach().contiguous(), u_target.detach().contiguous())
         ctx.save_for_backward(Md)
-        return 0.5 * torch.sum(d * Md)
+        return torch.tensor(loss, dtype=torch.float64, device=u.device)
 
     @staticmethod
     def backward(ctx, g: torch.Tensor):

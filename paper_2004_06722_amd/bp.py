@@ -202,3 +202,15 @@ class Operator:
         g = torch.empty((self.nelem, self.q ** 3), dtype=torch.float64, device=self.device)
         check(self._lib.bp_grad_kappa(self._h, _ptr(lam), _ptr(u), _ptr(g), _stream()))
         return g
+
+    def mass_misfit(self, u: torch.Tensor, u_target: torch.Tensor, grad: bool = True):
+        """L = 1/2 sum_c (u - u_t)_c^T M (u - u_t)_c with the unmasked mass
+        matrix, and M (u - u_t) (None without grad); bp_mass_misfit."""
+        self._vec(u, name="u")
+        self._vec(u_target, name="u_target")
+        g = torch.empty_like(u) if grad else None
+        loss = ctypes.c_double(0.0)
+        check(self._lib.bp_mass_misfit(self._h, _ptr(u), _ptr(u_target),
+                                       _ptr(g) if g is not None else None, ctypes.byref(loss),
+                                       _stream()))
+        return loss.value, g

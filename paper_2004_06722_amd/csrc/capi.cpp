@@ -1110,6 +1110,46 @@ int bp_grad_kappa(bp_op op, const double *lam, const double *u, double *g, void 
   return launch_grad_kappa(op, lam, u, g, s);
 }
 
+int bp_mass_misfit(bp_op op, const double *u, const double *u_target, double *grad,
+                   double *loss, void *stream) {
+  int rc = check_op(op);
+  if (rc) return rc;
+  if (!u || !u_target || !loss) return set_error(BP_ERR_ARG, "bp_mass_misfit: NULL pointer");
+  if (grad && (grad == u || grad == u_target))
+    return set_error(BP_ERR_ARG, "bp_mass_misfit: grad must not alias an input");
+  hipStream_t s = (hipStream_t)stream;
+  const int nc = op->ncomp;
+  const int64_t n = op->nglobal, nv = n * nc;
+  // d = u - u_target in the internal order, in the operator's work vector r
+  if (op->perm) {
+    permute_in<double>(nc, n, op->perm, u, op->r, s);
+    permute_in<double>(nc, n, op->perm, u_target, op->pv, s);
+    difference(op->r, op->pv, op->r, nv, s);
+  } else {
+    difference(u, u_target, op->r, nv, s);
+  }
+  // M d (unmasked) with the element energies d_L^T B_L d_L per work-group
+  // and component, whose sum is d^T M d
+  double *pa = op->part + (vec_blocks(n) + kStage2Rows) * 3 * nc;
+  fill_f64(op->w, nv, 0.0, s);
+  rc = launch_apply(op, BP_MASS, false, op->r, op->w, false, pa, nullptr, s);
+  if (rc) return rc;
+  operator_energies(nc, pa, apply_rows(op, BP_MASS), op->sc, s);
+  if (grad) {
+    if (op->perm)
+      permute_out<double>(nc, n, op->iperm, op->w, grad, s);
+    else
+      BP_HIP(hipMemcpyAsync(grad, op->w, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  BP_HIP(hipGetLastError());
+  BP_HIP(hipMemcpyAsync(op->sc_host, op->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  BP_HIP(hipStreamSynchronize(s));
+  double e = 0.0;
+  for (int c = 0; c < nc; ++c) e += op->sc_host->pap[c];
+  *loss = 0.5 * e;
+  return BP_OK;
+}
+
 int bp_set_option(bp_op op, int option, int value) {
   if (!op) return set_error(BP_ERR_ARG, "null operator");
   // the resources an option needs are created here, so that the solves

@@ -171,6 +171,12 @@ template <typename T>
 void cg_restart(int nc, int64_t n, T *r, T *p, const T *dinv, double *part,
                 DevScalars *sc, hipStream_t s);
 
+// sc->pap[c] = sum over the rows of column c of the operator's energy table
+// part[rows][nc] (fixed order); part + rows nc holds the stage-1 rows
+void operator_energies(int nc, double *part, int64_t rows, DevScalars *sc, hipStream_t s);
+// d = a - b over count entries (d may be a)
+void difference(const double *a, const double *b, double *d, int64_t count, hipStream_t s);
+
 // defect correction helpers (FP64 outer loop)
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,
                  double *part, DevScalars *sc, hipStream_t s);

@@ -948,6 +948,26 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_norms(const double *__restr
     }
 }
 
+// sc->pap[c] = the sum of column c of part[nb][NC] in the fixed order of
+// reduce_columns (the energies u^T M u per component of a mass apply)
+template <int NC>
+__global__ __launch_bounds__(kFinThreads) void k_fin_energy(const double *__restrict__ part,
+                                                            int64_t nb, DevScalars *sc) {
+  __shared__ double res[NC];
+  reduce_columns<NC>(part, nb, res);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < NC; ++c) sc->pap[c] = res[c];
+}
+
+// d = a - b entry by entry (d may be a)
+__global__ __launch_bounds__(kVecThreads) void k_difference(const double *a,
+                                                            const double *__restrict__ b,
+                                                            double *d, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * kVecThreads)
+    d[i] = a[i] - b[i];
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_to_f32(const double *__restrict__ s,
                                                         float *__restrict__ d, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
@@ -1291,7 +1311,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_restart(const double *__res
   }
 }
 
-enum class FinKind { Init, Alpha, Beta, Norms, Restart };
+enum class FinKind { Init, Alpha, Beta, Norms, Restart, Energy };
 
 // the single-work-group finisher for nc components (compile-time widths)
 template <int NC>
@@ -1314,6 +1334,9 @@ static void launch_fin_nc(FinKind k, const double *src, int64_t rows, DevScalars
       break;
     case FinKind::Restart:
       hipLaunchKernelGGL(k_fin_restart<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
+      break;
+    case FinKind::Energy:
+      hipLaunchKernelGGL(k_fin_energy<NC>, dim3(1), dim3(kFinThreads), 0, s, src, rows, sc);
       break;
   }
 }
@@ -1583,6 +1606,17 @@ void cg_update_r_gather(int nc, int64_t n, int64_t nl, T *r, const T *wl, const 
     hipLaunchKernelGGL((k_cg_update_r_gather<T, false>), dim3(vec_blocks(n), nc),
                        dim3(kGroupThreads<T>), 0, s, n, nl, r, wl, off, pos, dinv, part, sc,
                        check ? 1 : 0);
+}
+
+void operator_energies(int nc, double *part, int64_t rows, DevScalars *sc, hipStream_t s) {
+  int64_t r = 0;
+  const double *src = reduce_stage1(part, rows, nc, part + rows * nc, &r, s);
+  launch_fin(FinKind::Energy, nc, src, r, sc, s);
+}
+
+void difference(const double *a, const double *b, double *d, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_difference, dim3(grid_blocks(count)), dim3(kVecThreads), 0, s, a, b, d,
+                     count);
 }
 
 void dc_residual(int nc, int64_t n, const double *b, double *r, double *w, const double *dinv,

@@ -28,6 +28,36 @@ def setup_case(p=3, grid=(3, 3, 3), ncomp=2):
     return c, kap, b, ut, disc_k
 
 
+@pytest.mark.parametrize("bp,p,ncomp,order", [(5, 3, 1, "internal"), (5, 7, 2, "caller"),
+                                               (6, 4, 3, "internal"), (1, 3, 1, "internal"),
+                                               (3, 5, 3, "internal"), (3, 2, 1, "scrambled")])
+def test_mass_misfit_matches_oracle(bp, p, ncomp, order):
+    # L = 1/2 sum_c d_c^T M d_c and M d (d = u - u_t, unmasked mass of the
+    # operator's own quadrature: GLL collocated for BP5/6, Gauss for BP1/3)
+    # against the oracle's loss and gradient; the fixed-order energy sum
+    # gives the same bits on a second call
+    grid = (3, 3, 3) if p <= 4 else (3, 2, 2)
+    c = Case(bp, p, *grid, seed=40 + p, ncomp=ncomp, caller_order=order == "caller",
+             scramble=7 if order == "scrambled" else None)
+    try:
+        u = synth.rhs_uniform(c.disc.nglobal, 41, ncomp=ncomp)
+        ut = synth.rhs_uniform(c.disc.nglobal, 51, ncomp=ncomp)
+        ud = torch.tensor(u.T.copy() if ncomp > 1 else u, device="cuda")
+        utd = torch.tensor(ut.T.copy() if ncomp > 1 else ut, device="cuda")
+        L, g = c.op.mass_misfit(ud, utd)
+        Lo = adjoint.loss(c.disc, u, ut)
+        go = adjoint.loss_grad_u(c.disc, u, ut)
+        assert abs(L - Lo) <= 1e-12 * abs(Lo), (L, Lo)
+        gh = g.cpu().numpy()
+        assert rel(gh.T if ncomp > 1 else gh, go) <= 1e-12
+        L2, g2 = c.op.mass_misfit(ud, utd, grad=False)
+        assert L2 == L and g2 is None
+        L0, g0 = c.op.mass_misfit(ud, ud)
+        assert L0 == 0.0 and float(torch.abs(g0).max()) == 0.0
+    finally:
+        c.close()
+
+
 def test_loss_and_gradients_match_oracle():
     from paper_2004_06722_amd.autograd import mass_norm_loss, poisson_solve
     c, kap, b, ut, disc_k = setup_case()
