@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def build(bp, N, k, ncomp=1, fp32=False):
+def build(bp, N, k, ncomp=1, fp32=False, caller_order=False):
     import paper_2004_06722_amd.bp as B
     q, quad = B.bp_quadrature(bp, N)
     ex, ey, ez = synth.element_grid(k) if isinstance(k, int) else k
@@ -25,7 +25,7 @@ def build(bp, N, k, ncomp=1, fp32=False):
     mesh = synth.brick_mesh(ex, ey, ez, N, xi, seed=0)
     dirich = mesh.boundary if bp >= 3 else None
     op = B.Operator(N, q, quad, mesh.elem_dofs, mesh.node_xyz, mesh.nglobal, dirich, ncomp=ncomp,
-                    fp32=fp32)
+                    fp32=fp32, caller_order=caller_order)
     return op, mesh, (ex, ey, ez), dirich
 
 
@@ -37,8 +37,8 @@ def sample_nodes(mesh, count, seed):
     return np.unique(nodes)
 
 
-def sampled_check(bp, N, k, ncomp=1, which=STIFF, count=48):
-    op, mesh, grid, dirich = build(bp, N, k, ncomp)
+def sampled_check(bp, N, k, ncomp=1, which=STIFF, count=48, caller_order=False):
+    op, mesh, grid, dirich = build(bp, N, k, ncomp, caller_order=caller_order)
     try:
         u = synth.rhs_uniform(mesh.nglobal, 11, ncomp=ncomp)      # [n] or [n, ncomp]
         w = op.apply(which, torch.from_numpy(np.ascontiguousarray(u.T)).cuda(),
@@ -105,9 +105,12 @@ def test_bp6_n7_e48cube_pcg_components_match_scalar_solves():
             op1.close()
 
 
-@pytest.mark.parametrize("bp,N,k", [(3, 7, 15), (1, 7, 15), (3, 3, 18), (1, 2, 20)])
-def test_bp1_bp3_sampled(bp, N, k):
-    op, _ = sampled_check(bp, N, k, which=MASS if bp == 1 else STIFF)
+@pytest.mark.parametrize("bp,N,k,caller_order", [(3, 7, 15, False), (1, 7, 15, False),
+                                                (1, 7, 15, True), (3, 3, 18, False),
+                                                (1, 2, 20, False)])
+def test_bp1_bp3_sampled(bp, N, k, caller_order):
+    # caller_order: the mass problems' benchmark set-up (the mesh's own numbering)
+    op, _ = sampled_check(bp, N, k, which=MASS if bp == 1 else STIFF, caller_order=caller_order)
     op.close()
 
 

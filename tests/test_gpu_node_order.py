@@ -29,7 +29,8 @@ def host(t):
 
 @pytest.mark.parametrize("caller_order", [False, True])
 @pytest.mark.parametrize("bp,p,ncomp,scramble", [(5, 7, 1, None), (5, 2, 2, 31), (3, 4, 1, None),
-                                                 (1, 5, 3, 32), (5, 8, 1, 33)])
+                                                 (1, 5, 3, 32), (5, 8, 1, 33), (1, 7, 1, None),
+                                                 (1, 7, 3, None)])
 def test_both_node_orders_match_the_oracle(bp, p, ncomp, scramble, caller_order):
     c = Case(bp, p, *((3, 3, 3) if p <= 4 else (3, 2, 2)), seed=p, ncomp=ncomp,
              scramble=scramble, caller_order=caller_order)
