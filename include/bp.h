@@ -23,6 +23,9 @@
  *   - Device pointers are owned by the caller; the library never frees them.
  *     Everything the library allocates belongs to the bp_op and is freed by
  *     bp_destroy.
+ *   - A bp_op's work vectors, partial-sum tables and device scalars are shared
+ *     by its calls: calls on one bp_op must not overlap (one stream, or the
+ *     caller orders them); different bp_op handles are independent.
  */
 #ifndef BP_H
 #define BP_H
