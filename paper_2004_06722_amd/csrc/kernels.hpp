@@ -404,8 +404,15 @@ __device__ __forceinline__ void stiff_colloc_body(
 // beta-scaled B~ read beside G (one more word per point). With the internal
 // node order (own) the element-interior nodes are stored, not added.
 // ---------------------------------------------------------------------------
+// Two waves per SIMD requested: it binds only from p1 = 11 in FP64 (the
+// p1 <= 10 and FP32 instances compile to the same code with or without it),
+// where the compiler otherwise let the register count pass 256 (p1 = 14) or
+// scheduled the same 252 registers differently (p1 = 13) (BK5 alone, N = 12:
+// 7.2 -> 10.0 TFLOP/s, N = 13: 7.3 -> 8.6;
+// BP5 iteration at N = 11: 2.09 -> 1.69 ms, N = 12: 2.53 -> 2.46 ms, E = 2^15),
+// at the cost of a few spilled registers at p1 = 13, 14.
 template <int P1, typename T, bool LOCAL = false, bool HELM = false>
-__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) void k_stiff_colloc(
+__global__ __launch_bounds__((Plane<P1, P1>::THREADS)) __attribute__((amdgpu_waves_per_eu(2))) void k_stiff_colloc(
     int64_t nelem, const int32_t *__restrict__ idx, const T *__restrict__ G,
     const T *__restrict__ Bb, const T *__restrict__ u, T *__restrict__ w, int ncomp, int c0,
     int masked, double *__restrict__ part, const int *__restrict__ done, int own) {
